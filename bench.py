@@ -1,0 +1,240 @@
+"""Benchmark: DRR forward + backward views/s, batched vs per-view, one GPU.
+
+Workload: 200 000 radiative Gaussians (log-scales ~ N(log 0.02, 0.3)),
+8 views of 512 x 512 at evenly spaced azimuths, L1 loss against a target
+rendered from a perturbed copy of the scene.  One step = the whole hot path
+for all views: preprocess, tile binning + radix sort, forward blending, L1
+upstream gradient, reverse blending, and the adjoint of the projection to
+every Gaussian parameter.  Inputs are resident in HBM before timing.
+
+Batched: all views in one set of launches.  Per-view: the same kernels with
+one view per launch sequence, looped over the views.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# algorithmic float32 operations (FMA = 2) per unit of work, counted from the
+# definition of Eq. 10 and its adjoint (see the design notes)
+FLOPS_EVAL = 14          # one alpha evaluation at a pixel (offset, exponent, exp, clamp, test)
+FLOPS_BLEND = 6          # blending a contributor (transmittance update, test, accumulate)
+FLOPS_ADJOINT = 28       # adjoint of one contributor (transmittance recovery, 7 gradients)
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--lds", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the DRR path is built and "
+              "measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import scenes as S
+    import paper_2403_04116_amd as P
+
+    dev = torch.device("cuda:0")
+    w = S.workload(args.workload)
+    g_np = S.scene(args.workload)
+    tgt_np = S.perturb(g_np, w.seeds["perturb"])
+    D = S.DETECTOR_SIDE
+    cams = P.cameras(w.angles, w.sizes, S.L_SO, S.L_SD, D, D)
+    st = P.settings(tile=args.tile, lds_batch=args.lds)
+    g = {k: torch.from_numpy(v).to(dev) for k, v in g_np.items()}
+    gt_t = {k: torch.from_numpy(v).to(dev) for k, v in tgt_np.items()}
+    npx = w.n_pixels
+    scale = 1.0 / npx
+
+    # target images (rendered once, outside timing)
+    tframe = P.Frame(w.n, cams, st, device=dev)
+    tframe.fit_capacity(gt_t)
+    target, _, _ = tframe.render_fwd(gt_t)
+    torch.cuda.synchronize()
+    del tframe
+
+    stream = torch.cuda.current_stream()
+
+    # ---- batched path -------------------------------------------------------
+    frame = P.Frame(w.n, cams, st, device=dev)
+    n_pairs = frame.fit_capacity(g)
+    out = frame.new_outputs()
+    dl = torch.empty(npx, dtype=torch.float32, device=dev)
+    grads = frame.new_grads(g)
+    gs = P.drr.gaussians_struct(g)
+    gr = P.XgGrads(*(grads[k].data_ptr() for k in P.drr.PARAMS))
+    sid = int(stream.cuda_stream)
+    image, final_t, n_contrib = out
+    ev = {k: [] for k in ("fwd0", "fwd1", "bwd0", "bwd1")}
+
+    def step_batched(record: bool):
+        for t in grads.values():
+            t.zero_()
+        P.xg_preprocess(frame.frame, gs, sid)
+        P.xg_bin_sort(frame.frame, sid)
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
+        if record:
+            e1 = torch.cuda.Event(enable_timing=True)
+            e1.record(stream)
+        P.xg_l1_grad(image.data_ptr(), target.data_ptr(), dl.data_ptr(), npx, scale, sid)
+        if record:
+            e2 = torch.cuda.Event(enable_timing=True)
+            e2.record(stream)
+        P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
+        if record:
+            e3 = torch.cuda.Event(enable_timing=True)
+            e3.record(stream)
+            ev["fwd0"].append(e0); ev["fwd1"].append(e1)
+            ev["bwd0"].append(e2); ev["bwd1"].append(e3)
+        P.xg_preprocess_bwd(frame.frame, gs, gr, sid)
+
+    def timed(fn, steps, warmup, **kw):
+        for _ in range(warmup):
+            fn(False, **kw) if kw else fn(False)
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        s0.record(stream)
+        for _ in range(steps):
+            fn(True, **kw) if kw else fn(True)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return s0.elapsed_time(s1) / steps, wall
+
+    ms_batched, wall_b = timed(step_batched, args.steps, args.warmup)
+    assert frame.status() == 0, "pair capacity exceeded during timing"
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev["fwd0"], ev["fwd1"])]))
+    bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev["bwd0"], ev["bwd1"])]))
+
+    counts = frame.render_counts().double().sum(dim=1).cpu().numpy()
+    evals, contribs, upto = (float(x) for x in counts)
+    fwd_flops = evals * FLOPS_EVAL + contribs * FLOPS_BLEND
+    bwd_flops = upto * FLOPS_EVAL + contribs * FLOPS_ADJOINT
+    if bwd_ms >= fwd_ms:
+        dom, dom_ms, dom_flops = "k_render_bwd", bwd_ms, bwd_flops
+    else:
+        dom, dom_ms, dom_flops = "k_render_fwd", fwd_ms, fwd_flops
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            if tj.get("kernel") == dom and tj.get("workload") == args.workload:
+                traffic = tj.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+
+    # ---- per-view path ------------------------------------------------------
+    per_view = None
+    if not args.no_per_view:
+        frames = []
+        off = 0
+        for v in range(w.n_views):
+            f = P.Frame(w.n, [cams[v]], st, device=dev)
+            f.fit_capacity(g)
+            wv, hv = w.sizes[v]
+            sl = slice(off, off + wv * hv)
+            frames.append((f, image[sl], final_t[sl], n_contrib[sl], dl[sl], target[sl], wv * hv))
+            off += wv * hv
+
+        def step_per_view(record: bool):
+            for t in grads.values():
+                t.zero_()
+            for f, im, ft, nc, d, tg, n in frames:
+                P.xg_preprocess(f.frame, gs, sid)
+                P.xg_bin_sort(f.frame, sid)
+                P.xg_render_fwd(f.frame, gs, im.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
+                P.xg_l1_grad(im.data_ptr(), tg.data_ptr(), d.data_ptr(), n, scale, sid)
+                P.xg_render_bwd(f.frame, d.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
+                P.xg_preprocess_bwd(f.frame, gs, gr, sid)
+
+        ms_pv, _ = timed(step_per_view, args.steps, args.warmup)
+        per_view = {"value": w.n_views / (ms_pv * 1e-3), "ms_per_step": ms_pv}
+
+    value = w.n_views / (ms_batched * 1e-3)
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of views ---------
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        st_o = O.Settings(tile=args.tile)
+        done_views = 0
+        t0 = time.perf_counter()
+        for v in range(w.n_views):
+            c = O.camera(w.angles[v], S.L_SO, S.L_SD, w.sizes[v][0], w.sizes[v][1], D, D)
+            pr = O.pairs(g_np, [c], st_o)
+            r = O.render_binned(g_np, [c], st_o, pr["values"], pr["ranges"])
+            prt = O.pairs(tgt_np, [c], st_o)
+            rt = O.render_binned(tgt_np, [c], st_o, prt["values"], prt["ranges"])
+            up = (np.sign(r["image"] - rt["image"]) * scale).astype(np.float32)
+            O.backward(g_np, [c], st_o, up, binned=(pr["values"], pr["ranges"]))
+            done_views += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": done_views / el, "unit": "views/s", "cores": O.threads(), "kind": "oracle",
+               "sample": f"{done_views} of {w.n_views} views, each: pair emission + sort, binned "
+                         f"forward, target forward, binned adjoint (FP64), {el:.1f} s"}
+
+    res = {
+        "metric": "DRR fwd+bwd views/s at 512^2, 200k Gaussians; batched vs per-view, same GPU",
+        "value": value,
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batched,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.n} Gaussians, {w.n_views} views of 512x512, L1, fwd+bwd",
+                   "gaussians": w.n, "views": w.n_views, "detector": "512x512",
+                   "tile": args.tile, "lds_batch": args.lds, "path": "batched"},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "launch_ms": dom_ms, "flops_per_launch": dom_flops},
+        "cpu_baseline": cpu,
+        "per_view": per_view,
+        "batched_over_per_view": (value / per_view["value"]) if per_view else None,
+        "kernels_ms": {"k_render_fwd": fwd_ms, "k_render_bwd": bwd_ms},
+        "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
+                 "revisited": upto},
+        "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),
+        "wall_s": wall_b,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

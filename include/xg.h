@@ -1,0 +1,231 @@
+/*
+ * xg.h -- C ABI of libxg, the gfx950 (MI355X) implementation of
+ * Differentiable Radiative Rasterization (DRR): tile-based splatting of
+ * radiative 3-D Gaussians through a circular cone-beam X-ray camera, and
+ * its backward pass to every Gaussian parameter.
+ *
+ * Paper: "Radiative Gaussian Splatting for Efficient X-ray Novel View
+ * Synthesis" (X-Gaussian).  The rendered image is I = F_DRR(M_ext, M_int,
+ * {G_i(mu_i, Sigma_i, alpha_i, f_i)}) of Eq. 5; the calls below split F_DRR
+ * into the stages of Sec. 3.2 and add its adjoint.
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers to caller-owned memory unless marked
+ *    [host].  The library never allocates, never frees and never
+ *    synchronises; compute calls only enqueue work on `stream` (a
+ *    hipStream_t; NULL = the null stream) and are safe under HIP graph
+ *    capture.
+ *  - Arguments are validated on the host before any HIP call; invalid
+ *    arguments return XG_EINVAL and enqueue nothing.  XG_EHIP reports a
+ *    failed kernel launch.  XG_ECAPACITY is raised asynchronously: when the
+ *    number of (view, Gaussian, tile) pairs exceeds the workspace capacity
+ *    the device status word is set (read it with xg_ws_layout offsets after
+ *    synchronising) and later stages leave their outputs undefined.
+ *  - Degenerate Gaussians (camera depth <= near_z, zero quaternion,
+ *    non-positive 2-D determinant, opacity < alpha_min, non-finite input,
+ *    footprint outside the detector) are culled: no pairs, zero gradient.
+ *  - Float arithmetic is IEEE binary32 except where noted; the depth and
+ *    bounding-rectangle computation ("key path") is a fixed binary32
+ *    operation sequence with no contraction, so sort keys are reproducible
+ *    bit for bit by any IEEE implementation.
+ */
+#ifndef XG_H
+#define XG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XG_ABI_VERSION 1
+
+typedef enum {
+    XG_OK = 0,
+    XG_EINVAL = 1,     /* invalid argument (synchronous, nothing enqueued) */
+    XG_ECAPACITY = 2,  /* pair capacity exceeded (device status word)      */
+    XG_EHIP = 3        /* a HIP runtime call or kernel launch failed       */
+} xg_status;
+
+/* One view.  Rotation/translation are rows 0..2 of M_ext and the focal
+ * lengths / principal point are M_int, both of Eq. 12.  pixel_offset and
+ * tile_offset place the view in the concatenated image buffers and in the
+ * global tile numbering; fill them with xg_layout_views.  80 bytes. */
+typedef struct {
+    float rot[9];          /* rotation block of M_ext, row-major            */
+    float trans[3];        /* translation column of M_ext: (0, 0, L_SO)      */
+    float fx, fy;          /* focal lengths, pixels                          */
+    float cx, cy;          /* principal point, pixels (W/2, H/2)             */
+    int32_t width, height; /* detector pixels                                */
+    int32_t pixel_offset;  /* index of pixel (0,0) in concatenated images    */
+    int32_t tile_offset;   /* global id of tile (0,0) for settings.tile      */
+} xg_camera;
+
+/* Renderer constants.  Defaults (xg_default_settings): tile 16,
+ * lds_batch 256, lowpass 0.3 px^2 added to the diagonal of the 2-D
+ * covariance, alpha_min 1/255, alpha_max 0.99, t_min 1e-4, near_z 0.2. */
+typedef struct {
+    int32_t tile;          /* 8 | 16 | 32: tile side and workgroup footprint */
+    int32_t lds_batch;     /* 64 | 128 | 256 Gaussians staged in LDS at once */
+    float lowpass;         /* k of Sigma'' + k I (>= 0)                       */
+    float alpha_min;       /* skip an evaluation with alpha < alpha_min      */
+    float alpha_max;       /* clamp alpha to alpha_max                        */
+    float t_min;           /* stop before transmittance drops below t_min    */
+    float near_z;          /* cull Gaussians with camera depth <= near_z     */
+    uint32_t flags;        /* XG_F_* bits                                     */
+} xg_settings;
+
+#define XG_F_PERSISTENT 1u /* render with a persistent grid over a tile queue */
+
+/* Gaussian parameters, float32, structure of arrays, contiguous:
+ * means[n][3], scales[n][3] (activated, > 0), quats[n][4] (w, x, y, z;
+ * any non-zero norm, normalised inside), opacity[n] (activated, in (0,1]),
+ * intensity[n] (activated view-independent radiation intensity, Eq. 3). */
+typedef struct {
+    const float *means, *scales, *quats, *opacity, *intensity;
+    int32_t n;
+} xg_gaussians;
+
+/* Gradients of the same shapes; xg_preprocess_bwd ACCUMULATES (+=) into them. */
+typedef struct {
+    float *means, *scales, *quats, *opacity, *intensity;
+} xg_grads;
+
+/* Everything that describes one rendering of n Gaussians into n_views
+ * views.  cams is a [host] array used for validation and launch shapes;
+ * cams_dev must hold the same n_views records in device memory.  ws is a
+ * device workspace of ws_bytes >= xg_workspace_size(...) bytes, 256-byte
+ * aligned; pair_capacity bounds the (view, Gaussian, tile) pairs it holds. */
+typedef struct {
+    int32_t n;
+    int32_t n_views;
+    const xg_camera *cams;      /* [host]   */
+    const xg_camera *cams_dev;  /* [device] */
+    xg_settings settings;
+    void *ws;
+    size_t ws_bytes;
+    int64_t pair_capacity;      /* 0 < pair_capacity < 2^31 */
+} xg_frame;
+
+/* Workspace sub-buffer offsets (bytes from ws), for inspection and tests. */
+typedef struct {
+    size_t status;      /* int32: XG_OK or XG_ECAPACITY                       */
+    size_t n_pairs;     /* int32: pairs emitted (may exceed the capacity)     */
+    size_t sort_sel;    /* int32: 0 -> keys0/values0 hold the sorted pairs, 1 -> keys1/values1 */
+    size_t depth_range; /* uint32[2]: min and max depth bits of kept Gaussians */
+    size_t records;     /* 48-byte render records per (view, Gaussian)        */
+    size_t counts;      /* uint32[n_views*n]: tiles touched (0 = culled)      */
+    size_t offsets;     /* uint32[n_views*n]: exclusive scan of counts        */
+    size_t keys0, keys1;     /* uint64[pair_capacity]                         */
+    size_t values0, values1; /* uint32[pair_capacity]                         */
+    size_t ranges;      /* uint32[total_tiles][2]: [start, end) per tile      */
+    size_t grad2d;      /* float[n_views*n][8]: per-view 2-D gradients        */
+    size_t total;       /* bytes needed                                       */
+} xg_ws_layout;
+
+/* Returns XG_ABI_VERSION. */
+int32_t xg_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char *xg_status_string(xg_status s);
+
+/* Name and description of the last HIP error seen by a call on this host
+ * thread that returned XG_EHIP ("hipSuccess" if none); static storage. */
+const char *xg_last_error(void);
+
+/* Default renderer constants. */
+xg_settings xg_default_settings(void);
+
+/* Camera of a circular cone-beam scanner (Eq. 12, W of Eq. 9): source at
+ * azimuth phi on a circle of radius l_so about the world z axis, elevation
+ * 0, flat detector of det_w x det_h scene units at distance l_sd from the
+ * source, sampled by width x height pixels.  Rows of M_ext are
+ * (-sin phi, cos phi, 0), (0, 0, -1), (-cos phi, -sin phi, 0) with
+ * translation (0, 0, l_so); focal lengths (l_sd * width) / det_w and
+ * (l_sd * height) / det_h pixels (the paper's L_SD with the pixel pitch made
+ * explicit); principal point (width/2, height/2).  float64 math rounded
+ * once to float32.  Leaves pixel_offset/tile_offset at 0.
+ * XG_EINVAL if out is NULL, width/height <= 0, or a length is not > 0. */
+xg_status xg_camera_from_scanner(double phi, double l_so, double l_sd, int32_t width,
+                                 int32_t height, double det_w, double det_h,
+                                 xg_camera *out /* [host] */);
+
+/* Fills pixel_offset and tile_offset of n_views [host] cameras for tile
+ * size `tile`: views are concatenated in order, tiles numbered row-major
+ * within a view.  Writes the totals if the pointers are non-NULL. */
+xg_status xg_layout_views(xg_camera *cams /* [host] */, int32_t n_views, int32_t tile,
+                          int64_t *total_pixels, int64_t *total_tiles);
+
+/* Workspace layout and size for a frame (only n, n_views, cams, settings
+ * and pair_capacity are read; ws may be NULL). */
+xg_status xg_ws_layout_of(const xg_frame *f /* [host] */, xg_ws_layout *out /* [host] */);
+
+/* Total workspace bytes for a frame (same inputs as xg_ws_layout_of). */
+xg_status xg_workspace_size(const xg_frame *f /* [host] */, size_t *bytes /* [host] */);
+
+/* Stage 1 (Eq. 7-9, Sec. 3.2): per (view, Gaussian) camera-space centre,
+ * depth, culling, 2-D covariance Sigma'' = J W Sigma W^T J^T (rows/cols 1-2)
+ * plus lowpass*I, its inverse in factored form, image-space centre, the
+ * integer bounding rectangle of the alpha >= alpha_min footprint and the
+ * number of tiles it touches.  Also resets the status word and clears the
+ * per-view 2-D gradient accumulators used by xg_render_bwd. */
+xg_status xg_preprocess(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                        void *stream);
+
+/* Stage 2 (Sec. 3.2): exclusive scan of the tile counts, emission of one
+ * (key, value) pair per (view, Gaussian, tile) with
+ * key = (global tile id << 32) | float32 bits of the camera depth and
+ * value = Gaussian index, a stable ascending radix sort of the pairs on the
+ * key bits that vary, and per-tile [start, end) ranges.  Equal keys keep
+ * ascending Gaussian index. */
+xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
+
+/* Stage 3 (Eq. 10): front-to-back blending of every pixel over its tile's
+ * sorted list: at pixel centre p + 1/2, alpha = min(alpha_max, o G) with
+ * G the projected 2-D Gaussian; evaluations outside the Gaussian's
+ * rectangle or with alpha < alpha_min are skipped; blending stops before a
+ * Gaussian that would take the transmittance below t_min.  Writes, per
+ * pixel of the concatenated images: image (sum of intensity*alpha*T,
+ * background 0), final_t (transmittance after the last contributor) and
+ * n_contrib (1-based position in the tile list of the last contributor,
+ * 0 if none). */
+xg_status xg_render_fwd(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                        float *image, float *final_t, int32_t *n_contrib, void *stream);
+
+/* Stage 4 (adjoint of Eq. 10): walks each pixel's list backwards from
+ * n_contrib, recovering the transmittance by division instead of reading
+ * stored per-contributor values, and accumulates per (view, Gaussian) the
+ * 2-D gradients (image-space centre, inverse 2-D covariance, opacity,
+ * intensity) in the workspace, reduced across each wavefront before one
+ * atomic add per (Gaussian, wavefront).  dl_dimage has the image layout;
+ * final_t and n_contrib are the forward's outputs.  Call once per
+ * xg_preprocess (which clears the accumulators). */
+xg_status xg_render_bwd(const xg_frame *f /* [host] */, const float *dl_dimage,
+                        const float *final_t, const int32_t *n_contrib, void *stream);
+
+/* Stage 5 (adjoint of Eq. 7-9): maps the 2-D gradients of every view to
+ * means, scales, quaternions (through their normalisation), opacity and
+ * intensity, summing over views in registers (one thread per Gaussian, no
+ * atomics), and ACCUMULATES into `grads` (caller zeroes them). */
+xg_status xg_preprocess_bwd(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                            const xg_grads *grads /* [host] */, void *stream);
+
+/* Per-pixel work counts of the forward definition, for throughput
+ * accounting and tests: counts[0][p] = evaluations (Gaussians of the list
+ * whose rectangle holds p, visited up to and including the one that ends
+ * blending), counts[1][p] = contributors, counts[2][p] = evaluations up to
+ * the last contributor (what the backward revisits).  counts is int32
+ * [3][total pixels]. */
+xg_status xg_render_counts(const xg_frame *f /* [host] */, int32_t *counts, void *stream);
+
+/* L1 term of Eq. 11: dl_dimage[p] = scale * sign(image[p] - target[p])
+ * (0 where equal), for n_pixels pixels. */
+xg_status xg_l1_grad(const float *image, const float *target, float *dl_dimage,
+                     int64_t n_pixels, float scale, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XG_H */

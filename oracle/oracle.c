@@ -409,10 +409,11 @@ static void blend_pixel(int32_t px, int32_t py, const int32_t *order, int64_t le
         int clamped = a > amax;
         double alpha = clamped ? amax : a;
         if (fabs(a - amax) <= DELTA_CLAMP * amax) { flags |= FLAG_CLAMP; ++nflag; }
-        if (fabs(alpha - amin) <= DELTA_ALPHA * amin) { flags |= FLAG_ALPHA_MIN; ++nflag; }
+        /* a zero threshold cannot be crossed by rounding (alpha >= 0, T >= 0) */
+        if (amin > 0.0 && fabs(alpha - amin) <= DELTA_ALPHA * amin) { flags |= FLAG_ALPHA_MIN; ++nflag; }
         if (alpha < amin) continue;
         double Tn = T * (1.0 - alpha);
-        if (fabs(Tn - tmin) <= DELTA_T * tmin) { flags |= FLAG_T_MIN; ++nflag; }
+        if (tmin > 0.0 && fabs(Tn - tmin) <= DELTA_T * tmin) { flags |= FLAG_T_MIN; ++nflag; }
         if (Tn < tmin) break;
         if (out_list) {
             contrib_t *cb = &out_list[nc];

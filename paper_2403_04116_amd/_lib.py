@@ -1,0 +1,197 @@
+"""ctypes binding of libxg (include/xg.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and raises
+XgError on a non-XG_OK status.  Device pointers are passed as integers
+(e.g. ``tensor.data_ptr()``); ``stream`` is a hipStream_t as an integer
+(``torch.cuda.current_stream().cuda_stream``) or 0.  There is no fallback:
+if libxg.so is missing the import of this module fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+# torch ships its own HIP runtime (libamdhip64.so, SONAME libamdhip64.so.7).
+# Loading it before libxg.so makes libxg's libamdhip64.so.7 dependency bind
+# to that same copy; loading libxg first would bring in a second HIP/HSA
+# runtime that does not know torch's device pointers and streams.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxg.so")
+
+XG_OK, XG_EINVAL, XG_ECAPACITY, XG_EHIP = 0, 1, 2, 3
+XG_F_PERSISTENT = 1
+ABI_VERSION = 1
+
+
+class XgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = f"{where}: {status_string(status)}"
+        if status == XG_EHIP:
+            msg += f" ({_L.xg_last_error().decode()})"
+        super().__init__(msg)
+        self.status = status
+
+
+class XgCamera(C.Structure):
+    _fields_ = [("rot", C.c_float * 9), ("trans", C.c_float * 3), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32),
+                ("pixel_offset", C.c_int32), ("tile_offset", C.c_int32)]
+
+
+class XgSettings(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("lds_batch", C.c_int32), ("lowpass", C.c_float),
+                ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("near_z", C.c_float), ("flags", C.c_uint32)]
+
+
+class XgGaussians(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("intensity", C.c_void_p), ("n", C.c_int32)]
+
+
+class XgGrads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("intensity", C.c_void_p)]
+
+
+class XgFrame(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_views", C.c_int32), ("cams", C.POINTER(XgCamera)),
+                ("cams_dev", C.c_void_p), ("settings", XgSettings), ("ws", C.c_void_p),
+                ("ws_bytes", C.c_size_t), ("pair_capacity", C.c_int64)]
+
+
+class XgWsLayout(C.Structure):
+    _fields_ = [(k, C.c_size_t) for k in (
+        "status", "n_pairs", "sort_sel", "depth_range", "records", "counts", "offsets",
+        "keys0", "keys1", "values0", "values1", "ranges", "grad2d", "total")]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(the DRR path has no CPU fallback)")
+
+_L = C.CDLL(LIB_PATH)
+_P = C.c_void_p
+_S = C.c_int
+
+_L.xg_abi_version.restype = C.c_int32
+_L.xg_status_string.restype = C.c_char_p
+_L.xg_status_string.argtypes = [_S]
+_L.xg_default_settings.restype = XgSettings
+_L.xg_camera_from_scanner.restype = _S
+_L.xg_camera_from_scanner.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                      C.c_double, C.c_double, C.POINTER(XgCamera)]
+_L.xg_layout_views.restype = _S
+_L.xg_layout_views.argtypes = [C.POINTER(XgCamera), C.c_int32, C.c_int32,
+                               C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+_L.xg_ws_layout_of.restype = _S
+_L.xg_ws_layout_of.argtypes = [C.POINTER(XgFrame), C.POINTER(XgWsLayout)]
+_L.xg_workspace_size.restype = _S
+_L.xg_workspace_size.argtypes = [C.POINTER(XgFrame), C.POINTER(C.c_size_t)]
+_L.xg_preprocess.restype = _S
+_L.xg_preprocess.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P]
+_L.xg_bin_sort.restype = _S
+_L.xg_bin_sort.argtypes = [C.POINTER(XgFrame), _P]
+_L.xg_render_fwd.restype = _S
+_L.xg_render_fwd.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P]
+_L.xg_render_bwd.restype = _S
+_L.xg_render_bwd.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P]
+_L.xg_preprocess_bwd.restype = _S
+_L.xg_preprocess_bwd.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), C.POINTER(XgGrads), _P]
+_L.xg_render_counts.restype = _S
+_L.xg_render_counts.argtypes = [C.POINTER(XgFrame), _P, _P]
+_L.xg_last_error.restype = C.c_char_p
+_L.xg_l1_grad.restype = _S
+_L.xg_l1_grad.argtypes = [_P, _P, _P, C.c_int64, C.c_float, _P]
+
+if _L.xg_abi_version() != ABI_VERSION:
+    raise ImportError("libxg.so ABI version mismatch; rebuild it")
+
+EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_camera_from_scanner",
+            "xg_layout_views", "xg_ws_layout_of", "xg_workspace_size", "xg_preprocess",
+            "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
+            "xg_render_counts", "xg_l1_grad", "xg_last_error")
+
+
+def lib() -> C.CDLL:
+    return _L
+
+
+def _check(st: int, where: str) -> None:
+    if st != XG_OK:
+        raise XgError(st, where)
+
+
+def status_string(st: int) -> str:
+    return _L.xg_status_string(st).decode()
+
+
+def xg_abi_version() -> int:
+    return int(_L.xg_abi_version())
+
+
+def xg_default_settings() -> XgSettings:
+    return _L.xg_default_settings()
+
+
+def xg_camera_from_scanner(phi, l_so, l_sd, width, height, det_w, det_h) -> XgCamera:
+    c = XgCamera()
+    _check(_L.xg_camera_from_scanner(phi, l_so, l_sd, width, height, det_w, det_h, C.byref(c)),
+           "xg_camera_from_scanner")
+    return c
+
+
+def xg_layout_views(cams, tile: int):
+    """cams: ctypes array of XgCamera (modified in place).  Returns (pixels, tiles)."""
+    px, tl = C.c_int64(), C.c_int64()
+    _check(_L.xg_layout_views(cams, len(cams), tile, C.byref(px), C.byref(tl)), "xg_layout_views")
+    return px.value, tl.value
+
+
+def xg_ws_layout_of(frame: XgFrame) -> XgWsLayout:
+    out = XgWsLayout()
+    _check(_L.xg_ws_layout_of(C.byref(frame), C.byref(out)), "xg_ws_layout_of")
+    return out
+
+
+def xg_workspace_size(frame: XgFrame) -> int:
+    b = C.c_size_t()
+    _check(_L.xg_workspace_size(C.byref(frame), C.byref(b)), "xg_workspace_size")
+    return b.value
+
+
+def xg_preprocess(frame: XgFrame, g: XgGaussians, stream: int = 0) -> None:
+    _check(_L.xg_preprocess(C.byref(frame), C.byref(g), stream), "xg_preprocess")
+
+
+def xg_bin_sort(frame: XgFrame, stream: int = 0) -> None:
+    _check(_L.xg_bin_sort(C.byref(frame), stream), "xg_bin_sort")
+
+
+def xg_render_fwd(frame: XgFrame, g: XgGaussians, image: int, final_t: int, n_contrib: int,
+                  stream: int = 0) -> None:
+    _check(_L.xg_render_fwd(C.byref(frame), C.byref(g), image, final_t, n_contrib, stream),
+           "xg_render_fwd")
+
+
+def xg_render_bwd(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int,
+                  stream: int = 0) -> None:
+    _check(_L.xg_render_bwd(C.byref(frame), dl_dimage, final_t, n_contrib, stream),
+           "xg_render_bwd")
+
+
+def xg_preprocess_bwd(frame: XgFrame, g: XgGaussians, grads: XgGrads, stream: int = 0) -> None:
+    _check(_L.xg_preprocess_bwd(C.byref(frame), C.byref(g), C.byref(grads), stream),
+           "xg_preprocess_bwd")
+
+
+def xg_render_counts(frame: XgFrame, counts: int, stream: int = 0) -> None:
+    _check(_L.xg_render_counts(C.byref(frame), counts, stream), "xg_render_counts")
+
+
+def xg_l1_grad(image: int, target: int, dl_dimage: int, n_pixels: int, scale: float,
+               stream: int = 0) -> None:
+    _check(_L.xg_l1_grad(image, target, dl_dimage, n_pixels, scale, stream), "xg_l1_grad")

@@ -1,0 +1,351 @@
+// Host side of the C ABI declared in include/xg.h: argument validation
+// (before any HIP call), workspace layout, and the launch sequence of each
+// stage on the caller's stream.  Nothing here allocates or synchronises.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.h"
+
+using namespace xg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool valid_settings(const xg_settings &s) {
+    if (s.tile != 8 && s.tile != 16 && s.tile != 32) return false;
+    if (s.lds_batch != 64 && s.lds_batch != 128 && s.lds_batch != 256) return false;
+    if (!(s.lowpass >= 0.0f) || !isfinite(s.lowpass)) return false;
+    if (!(s.alpha_min >= 0.0f && s.alpha_min < 1.0f)) return false;
+    if (!(s.alpha_max > 0.0f && s.alpha_max <= 1.0f)) return false;
+    if (!(s.alpha_min <= s.alpha_max)) return false;
+    if (!(s.t_min >= 0.0f && s.t_min < 1.0f)) return false;
+    if (!isfinite(s.near_z)) return false;
+    if (s.flags & ~XG_F_PERSISTENT) return false;
+    return true;
+}
+
+int64_t tiles_of(const xg_camera &c, int tile) {
+    return (int64_t)((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
+}
+
+// Validates the host-side description of a frame.  Checks the cameras'
+// offsets against the layout implied by their order and the tile size.
+xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t *tot_tiles) {
+    if (!f) return XG_EINVAL;
+    if (f->n < 0 || f->n_views < 1 || !f->cams) return XG_EINVAL;
+    if (!valid_settings(f->settings)) return XG_EINVAL;
+    if (f->pair_capacity <= 0 || f->pair_capacity >= (1ll << 31)) return XG_EINVAL;
+    if ((int64_t)f->n * f->n_views >= (1ll << 32)) return XG_EINVAL;
+    int64_t px = 0, tl = 0;
+    for (int v = 0; v < f->n_views; ++v) {
+        const xg_camera &c = f->cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 32767 || c.height > 32767) return XG_EINVAL;
+        if (c.pixel_offset != px || c.tile_offset != tl) return XG_EINVAL;
+        for (int k = 0; k < 9; ++k)
+            if (!isfinite(c.rot[k])) return XG_EINVAL;
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(c.trans[k])) return XG_EINVAL;
+        if (!isfinite(c.fx) || !isfinite(c.fy) || !isfinite(c.cx) || !isfinite(c.cy)) return XG_EINVAL;
+        px += (int64_t)c.width * c.height;
+        tl += tiles_of(c, f->settings.tile);
+    }
+    if (px >= (1ll << 31) || tl >= (1ll << 31)) return XG_EINVAL;
+    if (need_ws) {
+        if (!f->cams_dev || !f->ws) return XG_EINVAL;
+        if (((uintptr_t)f->ws) % kAlign != 0) return XG_EINVAL;
+    }
+    if (tot_px) *tot_px = px;
+    if (tot_tiles) *tot_tiles = tl;
+    return XG_OK;
+}
+
+struct Plan {
+    xg_ws_layout lay;
+    size_t depth_part, scan_tmp, hist, hist_tmp, tile_order;
+    int64_t total_px, total_tiles, n_items;
+    int32_t hist_blocks;
+};
+
+xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
+    xg_status st = check_frame(f, need_ws, &P.total_px, &P.total_tiles);
+    if (st != XG_OK) return st;
+    const int64_t ni = (int64_t)f->n * f->n_views;
+    const int64_t cap = f->pair_capacity;
+    P.n_items = ni;
+    P.hist_blocks = (int32_t)((cap + kSortBlock - 1) / kSortBlock);
+    const int64_t hist_n = (int64_t)kRadix * P.hist_blocks;
+    const int64_t scan_words = (ni + kScanBlock - 1) / kScanBlock + 1;
+    const int64_t part_words = 2 * ((ni + 255) / 256) + 2;
+    size_t o = 0;
+    xg_ws_layout &L = P.lay;
+    memset(&L, 0, sizeof(L));
+    L.status = 0;
+    L.n_pairs = offsetof(WsHeader, n_pairs);
+    L.sort_sel = offsetof(WsHeader, sort_sel);
+    L.depth_range = offsetof(WsHeader, depth_min);
+    o = sizeof(WsHeader);
+    L.records = o;            o = align_up(o + 48 * (size_t)ni);
+    L.counts = o;             o = align_up(o + 4 * (size_t)ni);
+    L.offsets = o;            o = align_up(o + 4 * (size_t)ni);
+    P.scan_tmp = o;           o = align_up(o + 4 * (size_t)(scan_words > part_words ? scan_words : part_words));
+    L.keys0 = o;              o = align_up(o + 8 * (size_t)cap);
+    L.keys1 = o;              o = align_up(o + 8 * (size_t)cap);
+    L.values0 = o;            o = align_up(o + 4 * (size_t)cap);
+    L.values1 = o;            o = align_up(o + 4 * (size_t)cap);
+    P.hist = o;               o = align_up(o + 4 * (size_t)hist_n);
+    P.hist_tmp = o;           o = align_up(o + 4 * (size_t)((hist_n + kScanBlock - 1) / kScanBlock + 1));
+    L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
+    L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
+    P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
+    L.total = o;
+    P.depth_part = P.scan_tmp;
+    if (need_ws && f->ws_bytes < L.total) return XG_EINVAL;
+    return XG_OK;
+}
+
+Ws resolve(const xg_frame *f, const Plan &P) {
+    char *b = (char *)f->ws;
+    Ws w;
+    w.hdr = (WsHeader *)b;
+    const int64_t ni = P.n_items;
+    w.rec.a = (float4 *)(b + P.lay.records);
+    w.rec.b = (float4 *)(b + P.lay.records + 16 * (size_t)ni);
+    w.rec.c = (int4 *)(b + P.lay.records + 32 * (size_t)ni);
+    w.counts = (uint32_t *)(b + P.lay.counts);
+    w.offsets = (uint32_t *)(b + P.lay.offsets);
+    w.scan_tmp = (uint32_t *)(b + P.scan_tmp);
+    w.keys[0] = (uint64_t *)(b + P.lay.keys0);
+    w.keys[1] = (uint64_t *)(b + P.lay.keys1);
+    w.values[0] = (uint32_t *)(b + P.lay.values0);
+    w.values[1] = (uint32_t *)(b + P.lay.values1);
+    w.hist = (uint32_t *)(b + P.hist);
+    w.hist_tmp = (uint32_t *)(b + P.hist_tmp);
+    w.ranges = (uint32_t *)(b + P.lay.ranges);
+    w.grad2d = (float *)(b + P.lay.grad2d);
+    w.tile_order = (int32_t *)(b + P.tile_order);
+    w.cap = f->pair_capacity;
+    w.n_items = ni;
+    w.total_tiles = P.total_tiles;
+    w.total_pixels = P.total_px;
+    w.n = f->n;
+    w.n_views = f->n_views;
+    w.tile_bits = P.total_tiles <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(P.total_tiles - 1));
+    w.hist_blocks = P.hist_blocks;
+    return w;
+}
+
+Params params_of(const xg_settings &s) {
+    Params p;
+    p.lowpass = s.lowpass;
+    p.alpha_min = s.alpha_min;
+    p.alpha_max = s.alpha_max;
+    p.t_min = s.t_min;
+    p.near_z = s.near_z;
+    // squared Mahalanobis radius beyond which o * exp(-m^2/2) < alpha_min
+    // for any o <= 1; +inf when alpha_min == 0
+    p.kappa = (float)(-2.0 * log((double)s.alpha_min));
+    p.tile = s.tile;
+    p.lds_batch = s.lds_batch;
+    return p;
+}
+
+bool valid_gaussians(const xg_gaussians *g, int32_t n) {
+    if (!g || g->n != n) return false;
+    if (n > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->intensity)) return false;
+    return true;
+}
+
+thread_local hipError_t g_last_error = hipSuccess;
+
+xg_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return XG_OK;
+    g_last_error = e;
+    return XG_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t xg_abi_version(void) { return XG_ABI_VERSION; }
+
+const char *xg_status_string(xg_status s) {
+    switch (s) {
+        case XG_OK: return "XG_OK";
+        case XG_EINVAL: return "XG_EINVAL: invalid argument";
+        case XG_ECAPACITY: return "XG_ECAPACITY: pair capacity exceeded";
+        case XG_EHIP: return "XG_EHIP: HIP launch failed";
+    }
+    return "unknown xg_status";
+}
+
+const char *xg_last_error(void) {
+    static thread_local char buf[256];
+    snprintf(buf, sizeof(buf), "%s: %s", hipGetErrorName(g_last_error),
+             hipGetErrorString(g_last_error));
+    return buf;
+}
+
+xg_settings xg_default_settings(void) {
+    xg_settings s;
+    s.tile = 16;
+    s.lds_batch = 256;
+    s.lowpass = 0.3f;
+    s.alpha_min = 1.0f / 255.0f;
+    s.alpha_max = 0.99f;
+    s.t_min = 1e-4f;
+    s.near_z = 0.2f;
+    s.flags = 0;
+    return s;
+}
+
+xg_status xg_camera_from_scanner(double phi, double l_so, double l_sd, int32_t width, int32_t height,
+                                 double det_w, double det_h, xg_camera *out) {
+    if (!out || width < 1 || height < 1) return XG_EINVAL;
+    if (!(l_so > 0.0) || !(l_sd > 0.0) || !(det_w > 0.0) || !(det_h > 0.0) || !isfinite(phi))
+        return XG_EINVAL;
+    const double sp = sin(phi), cp = cos(phi);
+    const double rot[9] = {-sp, cp, 0.0, 0.0, 0.0, -1.0, -cp, -sp, 0.0};
+    memset(out, 0, sizeof(*out));
+    for (int k = 0; k < 9; ++k) out->rot[k] = (float)rot[k];
+    out->trans[2] = (float)l_so;
+    out->fx = (float)((l_sd * (double)width) / det_w);
+    out->fy = (float)((l_sd * (double)height) / det_h);
+    out->cx = (float)((double)width / 2.0);
+    out->cy = (float)((double)height / 2.0);
+    out->width = width;
+    out->height = height;
+    return XG_OK;
+}
+
+xg_status xg_layout_views(xg_camera *cams, int32_t n_views, int32_t tile, int64_t *total_pixels,
+                          int64_t *total_tiles) {
+    if (!cams || n_views < 1 || (tile != 8 && tile != 16 && tile != 32)) return XG_EINVAL;
+    int64_t px = 0, tl = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (cams[v].width < 1 || cams[v].height < 1) return XG_EINVAL;
+        if (px >= (1ll << 31) || tl >= (1ll << 31)) return XG_EINVAL;
+        cams[v].pixel_offset = (int32_t)px;
+        cams[v].tile_offset = (int32_t)tl;
+        px += (int64_t)cams[v].width * cams[v].height;
+        tl += tiles_of(cams[v], tile);
+    }
+    if (total_pixels) *total_pixels = px;
+    if (total_tiles) *total_tiles = tl;
+    return XG_OK;
+}
+
+xg_status xg_ws_layout_of(const xg_frame *f, xg_ws_layout *out) {
+    if (!out) return XG_EINVAL;
+    Plan P;
+    xg_status st = make_plan(f, false, P);
+    if (st != XG_OK) return st;
+    *out = P.lay;
+    return XG_OK;
+}
+
+xg_status xg_workspace_size(const xg_frame *f, size_t *bytes) {
+    if (!bytes) return XG_EINVAL;
+    Plan P;
+    xg_status st = make_plan(f, false, P);
+    if (st != XG_OK) return st;
+    *bytes = P.lay.total;
+    return XG_OK;
+}
+
+xg_status xg_preprocess(const xg_frame *f, const xg_gaussians *g, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n)) return XG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    hipError_t e = launch_reset(ws, s);
+    if (e == hipSuccess && ws.n_items > 0) e = launch_preprocess(ws, *g, f->cams_dev, p, s);
+    return hip_status(e);
+}
+
+xg_status xg_bin_sort(const xg_frame *f, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    hipError_t e = hipSuccess;
+    if (ws.n_items > 0) {
+        e = launch_scan(ws.counts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
+                        &ws.hdr->status, ws.cap, s);
+        if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
+        if (e == hipSuccess) e = launch_sort(ws, s);
+    }
+    if (e == hipSuccess) e = launch_ranges(ws, s);
+    return hip_status(e);
+}
+
+xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
+                        int32_t *n_contrib, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !image || !final_t || !n_contrib) return XG_EINVAL;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib,
+                                        (f->settings.flags & XG_F_PERSISTENT) != 0,
+                                        (hipStream_t)stream));
+}
+
+xg_status xg_render_bwd(const xg_frame *f, const float *dl_dimage, const float *final_t,
+                        const int32_t *n_contrib, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!dl_dimage || !final_t || !n_contrib) return XG_EINVAL;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_render_bwd(ws, f->cams_dev, p, dl_dimage, final_t, n_contrib,
+                                        (f->settings.flags & XG_F_PERSISTENT) != 0,
+                                        (hipStream_t)stream));
+}
+
+xg_status xg_preprocess_bwd(const xg_frame *f, const xg_gaussians *g, const xg_grads *grads,
+                            void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !grads) return XG_EINVAL;
+    if (f->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity ||
+                     !grads->intensity))
+        return XG_EINVAL;
+    if (f->n == 0) return XG_OK;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_preprocess_bwd(ws, *g, f->cams_dev, p, *grads, (hipStream_t)stream));
+}
+
+xg_status xg_render_counts(const xg_frame *f, int32_t *counts, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!counts) return XG_EINVAL;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_render_counts(ws, f->cams_dev, p, counts, (hipStream_t)stream));
+}
+
+xg_status xg_l1_grad(const float *image, const float *target, float *dl_dimage, int64_t n_pixels,
+                     float scale, void *stream) {
+    if (!image || !target || !dl_dimage || n_pixels < 0 || !isfinite(scale)) return XG_EINVAL;
+    if (n_pixels == 0) return XG_OK;
+    return hip_status(launch_l1_grad(image, target, dl_dimage, n_pixels, scale, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Internal definitions shared by the gfx950 kernels and the host ABI layer.
+// Nothing here is part of the public C ABI (include/xg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xg.h"
+
+namespace xg {
+
+constexpr int kWave = 64;
+
+// Workspace header words (first 256 bytes of the workspace).
+struct WsHeader {
+    int32_t status;        // XG_OK / XG_ECAPACITY
+    int32_t n_pairs;       // pairs requested by the scan (may exceed capacity)
+    int32_t sort_sel;      // which key/value buffer holds the sorted pairs
+    uint32_t depth_min;    // min float32 depth bits over kept (view, Gaussian)
+    uint32_t depth_max;    // max float32 depth bits
+    int32_t queue_fwd;     // persistent forward tile queue head
+    int32_t queue_bwd;     // persistent backward tile queue head
+    int32_t pad[57];
+};
+static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
+
+// Render record of one (view, Gaussian), written by the preprocess and read
+// by every tile that lists the Gaussian.  48 bytes in three 16-byte parts.
+//   a: (u_x - floor(u_x), u_y - floor(u_y), qa, qb)
+//   b: (qc, opacity, intensity, float bits of depth)
+//   c: (floor(u_x), floor(u_y), x_lo | x_hi << 16, y_lo | y_hi << 16)
+// (qa, qb, qc) factor the inverse 2-D covariance scaled by k = log2(e)/2:
+//   k * d^T Sigma''^-1 d = (qa dx + qb dy)^2 + (qc dy)^2
+// so that exp(-d^T Sigma''^-1 d / 2) = exp2(-(that)).
+struct Records {
+    float4 *a;
+    float4 *b;
+    int4 *c;
+};
+
+// Device view of a workspace, resolved on the host from the layout.
+struct Ws {
+    WsHeader *hdr;
+    Records rec;
+    uint32_t *counts;
+    uint32_t *offsets;
+    uint32_t *scan_tmp;
+    uint64_t *keys[2];
+    uint32_t *values[2];
+    uint32_t *hist;
+    uint32_t *hist_tmp;
+    uint32_t *ranges;
+    float *grad2d;
+    int32_t *tile_order;   // persistent queue: tiles in work order
+    int64_t cap;
+    int64_t n_items;       // n_views * n
+    int64_t total_tiles;
+    int64_t total_pixels;
+    int32_t n;
+    int32_t n_views;
+    int32_t tile_bits;     // bits of the largest global tile id
+    int32_t hist_blocks;   // radix-sort blocks for the capacity
+};
+
+// Scalar constants of one rendering.
+struct Params {
+    float lowpass, alpha_min, alpha_max, t_min, near_z;
+    float kappa;           // float32(-2 ln alpha_min): rectangle radius^2
+    int32_t tile;
+    int32_t lds_batch;
+};
+
+constexpr float kLog2eHalf = 0.72134752044448170368f;   // log2(e) / 2
+constexpr float kInvLog2eHalf = 1.38629436111989061883f; // 2 ln 2
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;   // 2048 elements
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortBlock = kSortThreads * kSortItems;   // 4096 pairs
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// ---- launchers (one translation unit per stage) --------------------------
+hipError_t launch_reset(const Ws &ws, hipStream_t s);
+hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
+                             const Params &p, hipStream_t s);
+hipError_t launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                       int32_t *total, int32_t *status, int64_t cap, hipStream_t s);
+hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s);
+hipError_t launch_sort(const Ws &ws, hipStream_t s);
+hipError_t launch_ranges(const Ws &ws, hipStream_t s);
+hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p,
+                             float *image, float *final_t, int32_t *n_contrib,
+                             int persistent, hipStream_t s);
+hipError_t launch_render_bwd(const Ws &ws, const xg_camera *cams, const Params &p,
+                             const float *dl_dimage, const float *final_t,
+                             const int32_t *n_contrib, int persistent, hipStream_t s);
+hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Params &p,
+                                int32_t *counts, hipStream_t s);
+hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
+                                 const Params &p, const xg_grads &gr, hipStream_t s);
+hipError_t launch_l1_grad(const float *image, const float *target, float *out, int64_t n,
+                          float scale, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// ---- device helpers ------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Wave-wide inclusive prefix sum of a uint32 (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, kWave);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive prefix sum over blockDim.x threads (multiple of 64,
+// at most 1024).  `lds` must hold blockDim.x / 64 + 1 words.  Returns the
+// exclusive prefix of v; *total receives the block sum.  Contains barriers.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds, uint32_t *total) {
+    const int l = lane_id();
+    const int w = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (l == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t x = (l < nw) ? lds[l] : 0u;
+        uint32_t xi = wave_incl_scan(x);
+        if (l < nw) lds[l] = xi - x;
+        if (l == nw - 1) lds[nw] = xi;
+    }
+    __syncthreads();
+    uint32_t res = lds[w] + inc - v;
+    *total = lds[nw];
+    __syncthreads();
+    return res;
+}
+
+// View index of a global tile id: the last view whose tile_offset <= tile.
+__device__ __forceinline__ int view_of_tile(const xg_camera *cams, int n_views, int tile) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cams[mid].tile_offset <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace xg

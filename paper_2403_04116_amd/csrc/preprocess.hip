@@ -1,0 +1,457 @@
+// Stage 1 and its adjoint: projection of radiative Gaussians through the
+// cone-beam camera (Eq. 7-9 and the 2-D covariance of Sec. 3.2), emission
+// of (tile | depth) keys, and the chain rule back to the 3-D parameters.
+//
+// One thread per (view, Gaussian) for the forward, one thread per Gaussian
+// (summing over views in registers, no atomics) for the adjoint.  These
+// kernels are HBM/latency bound and tiny next to the blending kernels.
+#include "common.h"
+
+#include <math.h>
+
+namespace xg {
+
+namespace {
+
+// Key path: depth, culling and integer bounding rectangle as a fixed
+// float32 operation sequence.  Every operation rounds once (IEEE RNE);
+// contraction into fused multiply-adds is disabled, '/' and sqrtf are the
+// correctly rounded forms, so the result is reproducible bit for bit.
+struct KeyOut {
+    float tz;
+    int xl, xh, yl, yh;
+};
+
+__device__ __noinline__ bool key_path(const float *m, const float *s, const float *q, float o,
+                                      const xg_camera &c, const Params &p, KeyOut &out) {
+#pragma clang fp contract(off)
+    const float *r = c.rot;
+    float mx = m[0], my = m[1], mz = m[2];
+    float tx = ((r[0] * mx + r[1] * my) + r[2] * mz) + c.trans[0];
+    float ty = ((r[3] * mx + r[4] * my) + r[5] * mz) + c.trans[1];
+    float tz = ((r[6] * mx + r[7] * my) + r[8] * mz) + c.trans[2];
+    if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) return false;
+    if (!(tz > p.near_z)) return false;
+    float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    if (!(n2 > 0.0f)) return false;
+    float nn = sqrtf(n2);
+    float w = qw / nn, x = qx / nn, y = qy / nn, z = qz / nn;
+    float R[9];
+    R[0] = 1.0f - 2.0f * (y * y + z * z);
+    R[1] = 2.0f * (x * y - w * z);
+    R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z);
+    R[4] = 1.0f - 2.0f * (x * x + z * z);
+    R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y);
+    R[7] = 2.0f * (y * z + w * x);
+    R[8] = 1.0f - 2.0f * (x * x + y * y);
+    float M[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        M[3 * a + 0] = R[3 * a + 0] * s[0];
+        M[3 * a + 1] = R[3 * a + 1] * s[1];
+        M[3 * a + 2] = R[3 * a + 2] * s[2];
+    }
+    float tz2 = tz * tz;
+    float J00 = c.fx / tz;
+    float J11 = c.fy / tz;
+    float J02 = -((c.fx * tx) / tz2);
+    float J12 = -((c.fy * ty) / tz2);
+    float A[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        A[k] = J00 * r[k] + J02 * r[6 + k];
+        A[3 + k] = J11 * r[3 + k] + J12 * r[6 + k];
+    }
+    float B[6];
+#pragma unroll
+    for (int row = 0; row < 2; ++row)
+#pragma unroll
+        for (int col = 0; col < 3; ++col)
+            B[3 * row + col] = (A[3 * row + 0] * M[col] + A[3 * row + 1] * M[3 + col])
+                               + A[3 * row + 2] * M[6 + col];
+    float sxx = ((B[0] * B[0] + B[1] * B[1]) + B[2] * B[2]) + p.lowpass;
+    float syy = ((B[3] * B[3] + B[4] * B[4]) + B[5] * B[5]) + p.lowpass;
+    float sxy = (B[0] * B[3] + B[1] * B[4]) + B[2] * B[5];
+    float det = sxx * syy - sxy * sxy;
+    if (!(det > 0.0f)) return false;
+    if (!(o >= p.alpha_min)) return false;
+    float ux = c.fx * (tx / tz) + c.cx;
+    float uy = c.fy * (ty / tz) + c.cy;
+    float rx = sqrtf(p.kappa * sxx);
+    float ry = sqrtf(p.kappa * syy);
+    float xl = ceilf((ux - rx) - 0.5f);
+    float xh = floorf((ux + rx) - 0.5f);
+    float yl = ceilf((uy - ry) - 0.5f);
+    float yh = floorf((uy + ry) - 0.5f);
+    float wmax = (float)(c.width - 1), hmax = (float)(c.height - 1);
+    if (!(xl <= xh) || !(xl <= wmax) || !(xh >= 0.0f)) return false;
+    if (!(yl <= yh) || !(yl <= hmax) || !(yh >= 0.0f)) return false;
+    out.tz = tz;
+    out.xl = (int)fmaxf(xl, 0.0f);
+    out.xh = (int)fminf(xh, wmax);
+    out.yl = (int)fmaxf(yl, 0.0f);
+    out.yh = (int)fminf(yh, hmax);
+    return true;
+}
+
+// Rotation matrix of a unit quaternion (w, x, y, z), float64.
+__device__ __forceinline__ void quat_rot(const double q[4], double R[9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Float64 projection of one Gaussian: camera-space centre t, the 2x3
+// matrix B = J W R diag(s) with Sigma'' = B B^T + k I, and Sigma''.
+struct Proj64 {
+    double t[3];
+    double qn;          // norm of the input quaternion
+    double q[4];        // unit quaternion
+    double R[9];
+    double J[6];        // first two rows of J (Eq. 9)
+    double A2[6];       // J W
+    double B[6];        // J W R diag(s)
+    double sxx, sxy, syy;
+};
+
+__device__ __forceinline__ void project64(const float *m, const float *s, const float *q,
+                                          const xg_camera &c, double lowpass, Proj64 &P) {
+    double r[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r[k] = (double)c.rot[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        P.t[a] = r[3 * a] * m[0] + r[3 * a + 1] * m[1] + r[3 * a + 2] * m[2] + (double)c.trans[a];
+    double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    P.qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    P.q[0] = q0 / P.qn; P.q[1] = q1 / P.qn; P.q[2] = q2 / P.qn; P.q[3] = q3 / P.qn;
+    quat_rot(P.q, P.R);
+    double fx = c.fx, fy = c.fy, tz = P.t[2];
+    P.J[0] = fx / tz; P.J[1] = 0.0; P.J[2] = -fx * P.t[0] / (tz * tz);
+    P.J[3] = 0.0; P.J[4] = fy / tz; P.J[5] = -fy * P.t[1] / (tz * tz);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            P.A2[3 * i + k] = P.J[3 * i] * r[k] + P.J[3 * i + 1] * r[3 + k] + P.J[3 * i + 2] * r[6 + k];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            P.B[3 * i + k] = (P.A2[3 * i] * P.R[k] + P.A2[3 * i + 1] * P.R[3 + k]
+                              + P.A2[3 * i + 2] * P.R[6 + k]) * (double)s[k];
+    P.sxx = P.B[0] * P.B[0] + P.B[1] * P.B[1] + P.B[2] * P.B[2] + lowpass;
+    P.syy = P.B[3] * P.B[3] + P.B[4] * P.B[4] + P.B[5] * P.B[5] + lowpass;
+    P.sxy = P.B[0] * P.B[3] + P.B[1] * P.B[4] + P.B[2] * P.B[5];
+}
+
+__global__ void k_reset(WsHeader *h) {
+    if (threadIdx.x == 0) {
+        h->status = XG_OK;
+        h->n_pairs = 0;
+        h->sort_sel = 0;
+        h->depth_min = 0xffffffffu;
+        h->depth_max = 0u;
+        h->queue_fwd = 0;
+        h->queue_bwd = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const xg_camera *cams,
+                                                    Params p, uint32_t *depth_part) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t dmin = 0xffffffffu, dmax = 0u;
+    if (idx < ws.n_items) {
+        const int v = (int)(idx / ws.n);
+        const int i = (int)(idx - (int64_t)v * ws.n);
+        const xg_camera &c = cams[v];
+        const float *m = g.means + 3 * (int64_t)i;
+        const float *s = g.scales + 3 * (int64_t)i;
+        const float *q = g.quats + 4 * (int64_t)i;
+        const float o = g.opacity[i];
+        KeyOut ko;
+        uint32_t count = 0;
+        if (key_path(m, s, q, o, c, p, ko)) {
+            Proj64 P;
+            project64(m, s, q, c, (double)p.lowpass, P);
+            double det = P.sxx * P.syy - P.sxy * P.sxy;
+            const double k = (double)kLog2eHalf;
+            // k d^T Sigma''^-1 d = (qa dx + qb dy)^2 + (qc dy)^2
+            double qa = sqrt(k * P.syy / det);
+            double qb = -k * P.sxy / (det * qa);
+            double qc = sqrt(k / P.syy);
+            double ux = (double)c.fx * P.t[0] / P.t[2] + (double)c.cx;
+            double uy = (double)c.fy * P.t[1] / P.t[2] + (double)c.cy;
+            double fx_ = floor(ux), fy_ = floor(uy);
+            fx_ = fmin(fmax(fx_, -1073741824.0), 1073741824.0);
+            fy_ = fmin(fmax(fy_, -1073741824.0), 1073741824.0);
+            uint32_t dbits = __float_as_uint(ko.tz);
+            ws.rec.a[idx] = make_float4((float)(ux - fx_), (float)(uy - fy_), (float)qa, (float)qb);
+            ws.rec.b[idx] = make_float4((float)qc, o, g.intensity[i], __uint_as_float(dbits));
+            ws.rec.c[idx] = make_int4((int)fx_, (int)fy_, ko.xl | (ko.xh << 16), ko.yl | (ko.yh << 16));
+            const int T = p.tile;
+            count = (uint32_t)((ko.xh / T - ko.xl / T + 1) * (ko.yh / T - ko.yl / T + 1));
+            dmin = dbits;
+            dmax = dbits;
+        }
+        ws.counts[idx] = count;
+        // clear this (view, Gaussian)'s 2-D gradient accumulator for the backward
+        float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d) + 2 * idx;
+        g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        g2[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // block min/max of the kept depths -> one partial per block
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, kWave));
+        dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, kWave));
+    }
+    __shared__ uint32_t smin[4], smax[4];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { smin[w] = dmin; smax[w] = dmax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) {
+            dmin = min(dmin, smin[k]);
+            dmax = max(dmax, smax[k]);
+        }
+        depth_part[2 * blockIdx.x] = dmin;
+        depth_part[2 * blockIdx.x + 1] = dmax;
+    }
+}
+
+// Reduces the per-block depth partials into the header (one block).
+__global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_t *part, int nparts) {
+    uint32_t dmin = 0xffffffffu, dmax = 0u;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
+        dmin = min(dmin, part[2 * k]);
+        dmax = max(dmax, part[2 * k + 1]);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, kWave));
+        dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, kWave));
+    }
+    __shared__ uint32_t smin[16], smax[16];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { smin[w] = dmin; smax[w] = dmax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) {
+            dmin = min(dmin, smin[k]);
+            dmax = max(dmax, smax[k]);
+        }
+        h->depth_min = dmin;
+        h->depth_max = dmax;
+    }
+}
+
+// Duplicate-with-key: one (key, value) per tile of the rectangle, at the
+// (view, Gaussian)'s scanned offset.  Pairs past the capacity are dropped
+// (the scan has raised XG_ECAPACITY).
+__global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int tile) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ws.n_items) return;
+    const uint32_t cnt = ws.counts[idx];
+    if (cnt == 0) return;
+    const uint32_t off = ws.offsets[idx];
+    if ((int64_t)off + cnt > ws.cap) return;
+    const int v = (int)(idx / ws.n);
+    const uint32_t i = (uint32_t)(idx - (int64_t)v * ws.n);
+    const int4 rc = ws.rec.c[idx];
+    const uint32_t dbits = __float_as_uint(ws.rec.b[idx].w);
+    const xg_camera &c = cams[v];
+    const int txn = (c.width + tile - 1) / tile;
+    const int tx0 = (rc.z & 0xffff) / tile, tx1 = (rc.z >> 16) / tile;
+    const int ty0 = (rc.w & 0xffff) / tile, ty1 = (rc.w >> 16) / tile;
+    uint64_t *kk = ws.keys[0] + off;
+    uint32_t *vv = ws.values[0] + off;
+    int n = 0;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            const uint64_t gt = (uint64_t)(c.tile_offset + ty * txn + tx);
+            kk[n] = (gt << 32) | dbits;
+            vv[n] = i;
+            ++n;
+        }
+}
+
+// Adjoint of the projection for one Gaussian, summed over views.
+// grad2d per (view, Gaussian): (dL/du_x, dL/du_y, dL/dA, dL/dB, dL/dC,
+// dL/do, dL/di, 0) with the inverse covariance [[A, B], [B, C]].
+__global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
+                                                        Params p, xg_grads gr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ws.n) return;
+    const float *m = g.means + 3 * (int64_t)i;
+    const float *s = g.scales + 3 * (int64_t)i;
+    const float *q = g.quats + 4 * (int64_t)i;
+    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0, gi = 0;
+    bool any = false;
+    for (int v = 0; v < ws.n_views; ++v) {
+        const int64_t idx = (int64_t)v * ws.n + i;
+        if (ws.counts[idx] == 0) continue;
+        const float4 g0 = reinterpret_cast<const float4 *>(ws.grad2d)[2 * idx];
+        const float4 g1 = reinterpret_cast<const float4 *>(ws.grad2d)[2 * idx + 1];
+        any = true;
+        go += g1.y;
+        gi += g1.z;
+        const xg_camera &c = cams[v];
+        Proj64 P;
+        project64(m, s, q, c, (double)p.lowpass, P);
+        double r[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) r[k] = (double)c.rot[k];
+        const double det = P.sxx * P.syy - P.sxy * P.sxy;
+        const double QA = P.syy / det, QB = -P.sxy / det, QC = P.sxx / det;
+        // dL/dSigma'' = -Q G_Q Q, off-diagonal of G_Q carrying half of dL/dB
+        const double gA = g0.z, gB = 0.5 * (double)g0.w, gC = g1.x;
+        const double T00 = gA * QA + gB * QB, T01 = gA * QB + gB * QC;
+        const double T10 = gB * QA + gC * QB, T11 = gB * QB + gC * QC;
+        const double GS00 = -(QA * T00 + QB * T10);
+        const double GS01 = -(QA * T01 + QB * T11);
+        const double GS10 = -(QB * T00 + QC * T10);
+        const double GS11 = -(QB * T01 + QC * T11);
+        const double gxx = GS00, gyy = GS11, gxy = GS01 + GS10;
+        // Sigma'' = B B^T + k I
+        double GB[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            GB[k] = 2.0 * gxx * P.B[k] + gxy * P.B[3 + k];
+            GB[3 + k] = 2.0 * gyy * P.B[3 + k] + gxy * P.B[k];
+        }
+        // B = A2 R diag(s): dL/d(R diag s) = A2^T GB, dL/dA2 = GB (R diag s)^T
+        double Ms[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Ms[3 * a + b] = P.R[3 * a + b] * (double)s[b];
+        double GA2[6];
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                GA2[3 * ii + a] = GB[3 * ii] * Ms[3 * a] + GB[3 * ii + 1] * Ms[3 * a + 1]
+                                  + GB[3 * ii + 2] * Ms[3 * a + 2];
+        double GR[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double gmab = P.A2[a] * GB[b] + P.A2[3 + a] * GB[3 + b];
+                gs[b] += gmab * P.R[3 * a + b];
+                GR[3 * a + b] = gmab * (double)s[b];
+            }
+        // rotation of the unit quaternion, then its normalisation
+        const double w = P.q[0], x = P.q[1], y = P.q[2], z = P.q[3];
+        double gw = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+        double gx = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5]
+                         + z * GR[6] + w * GR[7] - 2 * x * GR[8]);
+        double gy = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5]
+                         - w * GR[6] + z * GR[7] - 2 * y * GR[8]);
+        double gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4]
+                         + y * GR[5] + x * GR[6] + y * GR[7]);
+        const double dot = w * gw + x * gx + y * gy + z * gz;
+        gq[0] += (gw - w * dot) / P.qn;
+        gq[1] += (gx - x * dot) / P.qn;
+        gq[2] += (gy - y * dot) / P.qn;
+        gq[3] += (gz - z * dot) / P.qn;
+        // A2 = J W: dL/dJ = GA2 W^T (only the non-zero entries of J)
+        const double GJ00 = GA2[0] * r[0] + GA2[1] * r[1] + GA2[2] * r[2];
+        const double GJ02 = GA2[0] * r[6] + GA2[1] * r[7] + GA2[2] * r[8];
+        const double GJ11 = GA2[3] * r[3] + GA2[4] * r[4] + GA2[5] * r[5];
+        const double GJ12 = GA2[3] * r[6] + GA2[4] * r[7] + GA2[5] * r[8];
+        const double fx = c.fx, fy = c.fy, tx = P.t[0], ty = P.t[1], tz = P.t[2];
+        const double tz2 = tz * tz, tz3 = tz2 * tz;
+        const double gux = g0.x, guy = g0.y;
+        const double gtx = GJ02 * (-fx / tz2) + gux * (fx / tz);
+        const double gty = GJ12 * (-fy / tz2) + guy * (fy / tz);
+        const double gtz = GJ00 * (-fx / tz2) + GJ02 * (2.0 * fx * tx / tz3)
+                           + GJ11 * (-fy / tz2) + GJ12 * (2.0 * fy * ty / tz3)
+                           + gux * (-fx * tx / tz2) + guy * (-fy * ty / tz2);
+        // t = W mu + tau
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gm[a] += r[a] * gtx + r[3 + a] * gty + r[6 + a] * gtz;
+    }
+    if (!any) return;
+    float *om = gr.means + 3 * (int64_t)i;
+    float *os = gr.scales + 3 * (int64_t)i;
+    float *oq = gr.quats + 4 * (int64_t)i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { om[a] += (float)gm[a]; os[a] += (float)gs[a]; }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) oq[a] += (float)gq[a];
+    gr.opacity[i] += (float)go;
+    gr.intensity[i] += (float)gi;
+}
+
+__global__ __launch_bounds__(256) void k_l1_grad(const float *img, const float *tgt, float *out,
+                                                 int64_t n, float scale) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const float d = img[k] - tgt[k];
+        out[k] = d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+int grid_for(int64_t n, int threads, int max_blocks = 65536) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_reset(const Ws &ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws.hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
+                             const Params &p, hipStream_t s) {
+    const int64_t nb = (ws.n_items + 255) / 256;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    // depth partials live in the scan scratch; the count scan runs after
+    // k_depth_range has consumed them
+    uint32_t *part = ws.scan_tmp;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws, g, cams,
+                       p, part);
+    hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1024), 0, s, ws.hdr, part, (int)(nb > 0 ? nb : 1));
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s) {
+    const int64_t nb = (ws.n_items + 255) / 256;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws, cams, p.tile);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
+                                 const Params &p, const xg_grads &gr, hipStream_t s) {
+    const int nb = (ws.n + 255) / 256;
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, ws, g, cams, p, gr);
+    return hipGetLastError();
+}
+
+hipError_t launch_l1_grad(const float *image, const float *target, float *out, int64_t n,
+                          float scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_l1_grad, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, image, target, out,
+                       n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace xg

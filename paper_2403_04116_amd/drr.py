@@ -1,0 +1,220 @@
+"""Torch-facing wrapper of the DRR library: frames, workspaces, autograd.
+
+PyTorch supplies device memory, streams and autograd here; every step of
+the rendering runs in libxg's HIP kernels (see include/xg.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as X
+
+PARAMS = ("means", "scales", "quats", "opacity", "intensity")
+
+
+def settings(tile: int = 16, lds_batch: int = 256, lowpass: float = 0.3,
+             alpha_min: float = 1.0 / 255.0, alpha_max: float = 0.99, t_min: float = 1e-4,
+             near_z: float = 0.2, persistent: bool = False) -> X.XgSettings:
+    s = X.xg_default_settings()
+    s.tile, s.lds_batch, s.lowpass = tile, lds_batch, lowpass
+    s.alpha_min, s.alpha_max, s.t_min, s.near_z = alpha_min, alpha_max, t_min, near_z
+    s.flags = X.XG_F_PERSISTENT if persistent else 0
+    return s
+
+
+def cameras(angles, sizes, l_so: float, l_sd: float, det_w: float, det_h: float | None = None):
+    """One cone-beam camera per (azimuth, (width, height)) (Eq. 12)."""
+    det_h = det_w if det_h is None else det_h
+    return [X.xg_camera_from_scanner(float(a), l_so, l_sd, int(w), int(h), det_w, det_h)
+            for a, (w, h) in zip(angles, sizes)]
+
+
+def gaussians_struct(g: dict) -> X.XgGaussians:
+    n = g["means"].shape[0]
+    for k in PARAMS:
+        t = g[k]
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{k} must be a contiguous float32 CUDA tensor")
+    return X.XgGaussians(g["means"].data_ptr(), g["scales"].data_ptr(), g["quats"].data_ptr(),
+                         g["opacity"].data_ptr(), g["intensity"].data_ptr(), n)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Frame:
+    """n Gaussians rendered into a fixed list of views, with its workspace.
+
+    The workspace holds the sorted per-tile lists between the forward and
+    the backward call, so a Frame serves one forward/backward at a time.
+    """
+
+    def __init__(self, n: int, cams, st: X.XgSettings | None = None, pair_capacity: int | None = None,
+                 device: str | torch.device = "cuda"):
+        self.n = int(n)
+        self.settings = st if st is not None else settings()
+        self.cams = (X.XgCamera * len(cams))(*cams)
+        self.total_pixels, self.total_tiles = X.xg_layout_views(self.cams, self.settings.tile)
+        self.device = torch.device(device)
+        self.cams_dev = torch.frombuffer(bytearray(bytes(self.cams)), dtype=torch.uint8).to(self.device)
+        self.n_views = len(cams)
+        self.sizes = [(c.width, c.height) for c in cams]
+        self.capacity = int(pair_capacity) if pair_capacity else max(1 << 16, 6 * self.n * self.n_views)
+        self._allocate()
+
+    # -- workspace -----------------------------------------------------------
+    def _frame(self, ws_ptr: int = 0, ws_bytes: int = 0) -> X.XgFrame:
+        return X.XgFrame(self.n, self.n_views, self.cams, self.cams_dev.data_ptr(), self.settings,
+                         ws_ptr, ws_bytes, self.capacity)
+
+    def _allocate(self) -> None:
+        probe = self._frame()
+        self.layout = X.xg_ws_layout_of(probe)
+        size = self.layout.total
+        self._ws_buf = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws_buf.data_ptr()
+        self._ws_off = (-base) % 256
+        self.ws = self._ws_buf[self._ws_off:self._ws_off + size]
+        self.frame = self._frame(self.ws.data_ptr(), size)
+
+    def set_capacity(self, cap: int) -> None:
+        if cap != self.capacity:
+            self.capacity = int(cap)
+            self._allocate()
+
+    def ws_tensor(self, offset: int, dtype: torch.dtype, count: int) -> torch.Tensor:
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        return self.ws[offset:offset + count * itemsize].view(dtype)
+
+    def status(self) -> int:
+        return int(self.ws_tensor(self.layout.status, torch.int32, 1).item())
+
+    def n_pairs(self) -> int:
+        return int(self.ws_tensor(self.layout.n_pairs, torch.int32, 1).item())
+
+    def sorted_pairs(self):
+        """(keys, values, ranges) views of the sorted lists (synchronises)."""
+        p = self.n_pairs()
+        sel = int(self.ws_tensor(self.layout.sort_sel, torch.int32, 1).item())
+        ko = self.layout.keys1 if sel else self.layout.keys0
+        vo = self.layout.values1 if sel else self.layout.values0
+        keys = self.ws_tensor(ko, torch.int64, p)
+        vals = self.ws_tensor(vo, torch.int32, p)
+        ranges = self.ws_tensor(self.layout.ranges, torch.int32, 2 * self.total_tiles)
+        return keys, vals, ranges.view(self.total_tiles, 2)
+
+    # -- stages --------------------------------------------------------------
+    def preprocess_sort(self, g: dict, stream=None) -> None:
+        gs = gaussians_struct(g)
+        s = _stream(stream)
+        X.xg_preprocess(self.frame, gs, s)
+        X.xg_bin_sort(self.frame, s)
+
+    def fit_capacity(self, g: dict, headroom: float = 1.25) -> int:
+        """Runs preprocess + sort, grows the workspace if the pairs did not fit
+        (synchronises).  Returns the pair count."""
+        self.preprocess_sort(g)
+        p = self.n_pairs()
+        if self.status() == X.XG_ECAPACITY or p > self.capacity:
+            self.set_capacity(int(math.ceil(p * headroom)) + 1024)
+            self.preprocess_sort(g)
+            p = self.n_pairs()
+        if self.status() != X.XG_OK:
+            raise X.XgError(self.status(), "fit_capacity")
+        return p
+
+    def new_outputs(self):
+        px = self.total_pixels
+        return (torch.empty(px, dtype=torch.float32, device=self.device),
+                torch.empty(px, dtype=torch.float32, device=self.device),
+                torch.empty(px, dtype=torch.int32, device=self.device))
+
+    def render_fwd(self, g: dict, out=None, stream=None):
+        image, final_t, n_contrib = out if out is not None else self.new_outputs()
+        X.xg_render_fwd(self.frame, gaussians_struct(g), image.data_ptr(), final_t.data_ptr(),
+                        n_contrib.data_ptr(), _stream(stream))
+        return image, final_t, n_contrib
+
+    def forward(self, g: dict, out=None, stream=None):
+        self.preprocess_sort(g, stream)
+        return self.render_fwd(g, out, stream)
+
+    def new_grads(self, g: dict) -> dict:
+        return {k: torch.zeros_like(g[k]) for k in PARAMS}
+
+    def backward(self, g: dict, dl_dimage: torch.Tensor, final_t: torch.Tensor,
+                 n_contrib: torch.Tensor, grads: dict | None = None, stream=None) -> dict:
+        """Adjoint of forward(); once per forward (the 2-D accumulators are
+        cleared by the preprocess)."""
+        grads = self.new_grads(g) if grads is None else grads
+        gr = X.XgGrads(*(grads[k].data_ptr() for k in PARAMS))
+        s = _stream(stream)
+        X.xg_render_bwd(self.frame, dl_dimage.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), s)
+        X.xg_preprocess_bwd(self.frame, gaussians_struct(g), gr, s)
+        return grads
+
+    def render_counts(self, stream=None) -> torch.Tensor:
+        """Per-pixel [evaluations, contributors, evaluations up to the last
+        contributor] of the current sorted lists (int32 [3, pixels])."""
+        out = torch.empty((3, self.total_pixels), dtype=torch.int32, device=self.device)
+        X.xg_render_counts(self.frame, out.data_ptr(), _stream(stream))
+        return out
+
+    def split(self, flat: torch.Tensor):
+        """Per-view (H, W) views of a concatenated per-pixel buffer."""
+        out, o = [], 0
+        for w, h in self.sizes:
+            out.append(flat[o:o + w * h].view(h, w))
+            o += w * h
+        return out
+
+
+def l1_grad(image: torch.Tensor, target: torch.Tensor, scale: float, out: torch.Tensor | None = None,
+            stream=None) -> torch.Tensor:
+    """dL/dI of the L1 term of Eq. 11: scale * sign(image - target)."""
+    out = torch.empty_like(image) if out is None else out
+    X.xg_l1_grad(image.data_ptr(), target.data_ptr(), out.data_ptr(), image.numel(), scale,
+                 _stream(stream))
+    return out
+
+
+class DRRFunction(torch.autograd.Function):
+    """I = F_DRR(M_ext, M_int, {G_i}) (Eq. 5) with the hand-written backward.
+
+    Saves only the final transmittance and the last contributor per pixel;
+    the backward recomputes the transmittance by division.
+    """
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacity, intensity, frame: Frame):
+        g = {"means": means.contiguous(), "scales": scales.contiguous(), "quats": quats.contiguous(),
+             "opacity": opacity.contiguous(), "intensity": intensity.contiguous()}
+        image, final_t, n_contrib = frame.forward(g)
+        ctx.frame = frame
+        ctx.save_for_backward(g["means"], g["scales"], g["quats"], g["opacity"], g["intensity"],
+                              final_t, n_contrib)
+        ctx.mark_non_differentiable(final_t, n_contrib)
+        return image, final_t, n_contrib
+
+    @staticmethod
+    def backward(ctx, dl_dimage, _dt, _dn):
+        means, scales, quats, opacity, intensity, final_t, n_contrib = ctx.saved_tensors
+        g = {"means": means, "scales": scales, "quats": quats, "opacity": opacity,
+             "intensity": intensity}
+        grads = ctx.frame.backward(g, dl_dimage.contiguous(), final_t, n_contrib)
+        return (grads["means"], grads["scales"], grads["quats"], grads["opacity"],
+                grads["intensity"], None)
+
+
+def render(g: dict, frame: Frame):
+    """Differentiable render of all views; returns the concatenated image."""
+    image, _, _ = DRRFunction.apply(g["means"], g["scales"], g["quats"], g["opacity"],
+                                    g["intensity"], frame)
+    return image

@@ -1,0 +1,161 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/xg.h, and validates arguments on the host before
+any HIP call.  Also: the host camera (Eq. 12) equals the oracle's bit for bit.
+"""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenes as S
+
+P = pytest.importorskip("paper_2403_04116_amd")
+X = P._lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 11
+    lib = C.CDLL(X.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(X.EXPORTED)
+
+
+def test_abi_version_and_status_strings():
+    assert P.xg_abi_version() == 1
+    for st in (0, 1, 2, 3):
+        assert X.status_string(st).startswith("XG_")
+
+
+def test_struct_sizes_match_header():
+    assert C.sizeof(X.XgCamera) == 80
+    assert C.sizeof(X.XgSettings) == 32
+    assert C.sizeof(X.XgFrame) == 80
+
+
+@pytest.mark.parametrize("phi", [0.0, 0.7, math.pi / 2, math.pi, 5.5, 2 * math.pi])
+@pytest.mark.parametrize("wh", [(64, 64), (512, 512), (100, 37)])
+def test_camera_matches_oracle_bitwise(phi, wh):
+    w, h = wh
+    c = P.xg_camera_from_scanner(phi, 4.0, 6.0, w, h, S.DETECTOR_SIDE, 0.9 * S.DETECTOR_SIDE)
+    o = O.camera(phi, 4.0, 6.0, w, h, S.DETECTOR_SIDE, 0.9 * S.DETECTOR_SIDE)
+    # the first 72 bytes share one layout (rotation, translation, intrinsics, size)
+    assert bytes(c)[:72] == bytes(o)[:72]
+    assert c.pixel_offset == 0 and c.tile_offset == 0
+
+
+def test_layout_views():
+    cams = (X.XgCamera * 3)(*[P.xg_camera_from_scanner(0.1 * k, 4, 6, w, h, 5, 5)
+                             for k, (w, h) in enumerate([(64, 64), (37, 20), (128, 96)])])
+    px, tl = P.xg_layout_views(cams, 16)
+    assert px == 64 * 64 + 37 * 20 + 128 * 96
+    assert tl == 16 + 3 * 2 + 8 * 6
+    assert [c.pixel_offset for c in cams] == [0, 4096, 4096 + 740]
+    assert [c.tile_offset for c in cams] == [0, 16, 22]
+    px8, tl8 = P.xg_layout_views(cams, 8)
+    assert tl8 == 64 + 5 * 3 + 16 * 12
+
+
+def _frame(n=100, views=((64, 64),), tile=16, cap=1 << 16, **kw):
+    cams = (X.XgCamera * len(views))(*[P.xg_camera_from_scanner(0.3, 4, 6, w, h, 5, 5)
+                                       for w, h in views])
+    P.xg_layout_views(cams, tile if tile in (8, 16, 32) else 16)
+    st = P.settings(tile=16)
+    st.tile = tile
+    for k, v in kw.items():
+        setattr(st, k, v)
+    return X.XgFrame(n, len(views), cams, 0, st, 0, 0, cap), cams
+
+
+def test_workspace_size_grows_with_capacity_and_views():
+    f1, _ = _frame(cap=1000)
+    f2, _ = _frame(cap=100000)
+    f3, _ = _frame(cap=1000, views=((64, 64), (64, 64)))
+    s1, s2, s3 = (P.xg_workspace_size(f) for f in (f1, f2, f3))
+    assert s2 > s1 + 12 * (100000 - 1000) * 2 - 1
+    assert s3 > s1
+    lay = P.xg_ws_layout_of(f1)
+    assert lay.total == s1
+    offs = [lay.records, lay.counts, lay.offsets, lay.keys0, lay.keys1, lay.values0, lay.values1,
+            lay.ranges, lay.grad2d]
+    assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("tile", 12), ("lds_batch", 100), ("lowpass", -1.0), ("alpha_min", 1.0),
+    ("alpha_max", 0.0), ("t_min", 1.0), ("near_z", float("nan")), ("flags", 8)])
+def test_invalid_settings_rejected(field, value):
+    f, _ = _frame(**{field: value})
+    with pytest.raises(X.XgError) as e:
+        P.xg_workspace_size(f)
+    assert e.value.status == X.XG_EINVAL
+
+
+def test_invalid_frames_rejected_before_any_hip_call():
+    g = X.XgGaussians(0, 0, 0, 0, 0, 100)
+    f, cams = _frame()
+    # no device workspace / cameras: EINVAL
+    with pytest.raises(X.XgError):
+        P.xg_preprocess(f, g)
+    # inconsistent offsets
+    f2, cams2 = _frame(views=((64, 64), (32, 32)))
+    cams2[1].tile_offset = 3
+    with pytest.raises(X.XgError):
+        P.xg_workspace_size(f2)
+    # capacity out of range
+    for cap in (0, -5, 1 << 31):
+        f3, _ = _frame(cap=cap)
+        with pytest.raises(X.XgError):
+            P.xg_workspace_size(f3)
+    # bad detector sizes
+    with pytest.raises(X.XgError):
+        P.xg_camera_from_scanner(0.0, 4, 6, 0, 10, 5, 5)
+    with pytest.raises(X.XgError):
+        P.xg_camera_from_scanner(0.0, -4, 6, 10, 10, 5, 5)
+    # misaligned workspace pointer and too-small workspace
+    f4, _ = _frame()
+    need = P.xg_workspace_size(f4)
+    f4.cams_dev = 256
+    f4.ws = 256 + 8
+    f4.ws_bytes = need
+    with pytest.raises(X.XgError):
+        P.xg_bin_sort(f4)
+    f4.ws = 512
+    f4.ws_bytes = need - 1
+    with pytest.raises(X.XgError):
+        P.xg_bin_sort(f4)
+    # Gaussian count mismatch and null parameter pointers
+    f4.ws_bytes = need
+    with pytest.raises(X.XgError):
+        P.xg_preprocess(f4, X.XgGaussians(0, 0, 0, 0, 0, 99))
+    with pytest.raises(X.XgError):
+        P.xg_preprocess(f4, X.XgGaussians(0, 0, 0, 0, 0, 100))
+    with pytest.raises(X.XgError):
+        P.xg_l1_grad(0, 0, 0, 10, 1.0)
+
+
+def test_package_fails_loudly_without_library(tmp_path):
+    """The binding raises ImportError when libxg.so is absent (no CPU fallback)."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2403_04116_amd"
+    shutil.copytree(os.path.join(ROOT, "paper_2403_04116_amd"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2403_04116_amd"], cwd=tmp_path,
+                       capture_output=True, text=True)
+    assert r.returncode != 0 and "not built" in r.stderr
