@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds", type=int, default=256)
+    ap.add_argument("--persistent", type=int, default=1, help="persistent blending kernels (1/0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -63,7 +64,7 @@ def main():
     tgt_np = S.perturb(g_np, w.seeds["perturb"])
     D = S.DETECTOR_SIDE
     cams = P.cameras(w.angles, w.sizes, S.L_SO, S.L_SD, D, D)
-    st = P.settings(tile=args.tile, lds_batch=args.lds)
+    st = P.settings(tile=args.tile, lds_batch=args.lds, persistent=bool(args.persistent))
     g = {k: torch.from_numpy(v).to(dev) for k, v in g_np.items()}
     gt_t = {k: torch.from_numpy(v).to(dev) for k, v in tgt_np.items()}
     npx = w.n_pixels
@@ -220,7 +221,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.n} Gaussians, {w.n_views} views of 512x512, L1, fwd+bwd",
                    "gaussians": w.n, "views": w.n_views, "detector": "512x512",
-                   "tile": args.tile, "lds_batch": args.lds, "path": "batched"},
+                   "tile": args.tile, "lds_batch": args.lds, "persistent": bool(args.persistent),
+                   "path": "batched"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "launch_ms": dom_ms, "flops_per_launch": dom_flops},

@@ -114,7 +114,7 @@ typedef struct {
     size_t n_pairs;     /* int32: pairs emitted (may exceed the capacity)     */
     size_t sort_sel;    /* int32: 0 -> keys0/values0 hold the sorted pairs, 1 -> keys1/values1 */
     size_t depth_range; /* uint32[2]: min and max depth bits of kept Gaussians */
-    size_t records;     /* 48-byte render records per (view, Gaussian)        */
+    size_t records;     /* 64-byte render records per (view, Gaussian)        */
     size_t counts;      /* uint32[n_views*n]: tiles touched (0 = culled)      */
     size_t offsets;     /* uint32[n_views*n]: exclusive scan of counts        */
     size_t keys0, keys1;     /* uint64[pair_capacity]                         */

@@ -90,7 +90,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     L.sort_sel = offsetof(WsHeader, sort_sel);
     L.depth_range = offsetof(WsHeader, depth_min);
     o = sizeof(WsHeader);
-    L.records = o;            o = align_up(o + 48 * (size_t)ni);
+    L.records = o;            o = align_up(o + sizeof(Record) * (size_t)ni);
     L.counts = o;             o = align_up(o + 4 * (size_t)ni);
     L.offsets = o;            o = align_up(o + 4 * (size_t)ni);
     P.scan_tmp = o;           o = align_up(o + 4 * (size_t)(scan_words > part_words ? scan_words : part_words));
@@ -114,9 +114,7 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     Ws w;
     w.hdr = (WsHeader *)b;
     const int64_t ni = P.n_items;
-    w.rec.a = (float4 *)(b + P.lay.records);
-    w.rec.b = (float4 *)(b + P.lay.records + 16 * (size_t)ni);
-    w.rec.c = (int4 *)(b + P.lay.records + 32 * (size_t)ni);
+    w.rec = (Record *)(b + P.lay.records);
     w.counts = (uint32_t *)(b + P.lay.counts);
     w.offsets = (uint32_t *)(b + P.lay.offsets);
     w.scan_tmp = (uint32_t *)(b + P.scan_tmp);
@@ -287,6 +285,7 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
         if (e == hipSuccess) e = launch_sort(ws, s);
     }
     if (e == hipSuccess) e = launch_ranges(ws, s);
+    if (e == hipSuccess) e = launch_tile_order(ws, s);
     return hip_status(e);
 }
 

@@ -20,28 +20,47 @@ struct WsHeader {
     uint32_t depth_max;    // max float32 depth bits
     int32_t queue_fwd;     // persistent forward tile queue head
     int32_t queue_bwd;     // persistent backward tile queue head
-    int32_t pad[57];
+    int32_t done_fwd;      // persistent forward workgroups finished
+    int32_t done_bwd;      // persistent backward workgroups finished
+    int32_t pad[55];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
 
 // Render record of one (view, Gaussian), written by the preprocess and read
-// by every tile that lists the Gaussian.  48 bytes in three 16-byte parts.
+// by every tile that lists the Gaussian: 64 bytes, one cache line, so a
+// staged list entry is a single aligned gather.
 //   a: (u_x - floor(u_x), u_y - floor(u_y), qa, qb)
 //   b: (qc, opacity, intensity, float bits of depth)
 //   c: (floor(u_x), floor(u_y), x_lo | x_hi << 16, y_lo | y_hi << 16)
+//   d: unused
 // (qa, qb, qc) factor the inverse 2-D covariance scaled by k = log2(e)/2:
 //   k * d^T Sigma''^-1 d = (qa dx + qb dy)^2 + (qc dy)^2
 // so that exp(-d^T Sigma''^-1 d / 2) = exp2(-(that)).
-struct Records {
-    float4 *a;
-    float4 *b;
-    int4 *c;
+struct alignas(64) Record {
+    float4 a;
+    float4 b;
+    int4 c;
+    float4 d;
 };
+static_assert(sizeof(Record) == 64, "one cache line per record");
+
+// Number of XCDs workgroups are dealt to round-robin (MI355X: 8).  Used to
+// give each XCD a contiguous range of tiles, so the records its L2 caches
+// are shared by the tiles it renders.
+constexpr int kXcds = 8;
+
+// Tile of workgroup b in a grid of n tiles such that XCD b % kXcds takes a
+// contiguous block of tiles.  A bijection on [0, n) for any n.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b % kXcds, i = b / kXcds;
+    const int q = n / kXcds, r = n % kXcds;
+    return x * q + min(x, r) + i;
+}
 
 // Device view of a workspace, resolved on the host from the layout.
 struct Ws {
     WsHeader *hdr;
-    Records rec;
+    Record *rec;
     uint32_t *counts;
     uint32_t *offsets;
     uint32_t *scan_tmp;
@@ -92,6 +111,7 @@ hipError_t launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *t
 hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s);
 hipError_t launch_sort(const Ws &ws, hipStream_t s);
 hipError_t launch_ranges(const Ws &ws, hipStream_t s);
+hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              float *image, float *final_t, int32_t *n_contrib,
                              int persistent, hipStream_t s);

@@ -158,6 +158,8 @@ __global__ void k_reset(WsHeader *h) {
         h->depth_max = 0u;
         h->queue_fwd = 0;
         h->queue_bwd = 0;
+        h->done_fwd = 0;
+        h->done_bwd = 0;
     }
 }
 
@@ -190,9 +192,11 @@ __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const
             fx_ = fmin(fmax(fx_, -1073741824.0), 1073741824.0);
             fy_ = fmin(fmax(fy_, -1073741824.0), 1073741824.0);
             uint32_t dbits = __float_as_uint(ko.tz);
-            ws.rec.a[idx] = make_float4((float)(ux - fx_), (float)(uy - fy_), (float)qa, (float)qb);
-            ws.rec.b[idx] = make_float4((float)qc, o, g.intensity[i], __uint_as_float(dbits));
-            ws.rec.c[idx] = make_int4((int)fx_, (int)fy_, ko.xl | (ko.xh << 16), ko.yl | (ko.yh << 16));
+            Record &rec = ws.rec[idx];
+            rec.a = make_float4((float)(ux - fx_), (float)(uy - fy_), (float)qa, (float)qb);
+            rec.b = make_float4((float)qc, o, g.intensity[i], __uint_as_float(dbits));
+            rec.c = make_int4((int)fx_, (int)fy_, ko.xl | (ko.xh << 16), ko.yl | (ko.yh << 16));
+            rec.d = make_float4(0.f, 0.f, 0.f, 0.f);
             const int T = p.tile;
             count = (uint32_t)((ko.xh / T - ko.xl / T + 1) * (ko.yh / T - ko.yl / T + 1));
             dmin = dbits;
@@ -260,8 +264,8 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
     if ((int64_t)off + cnt > ws.cap) return;
     const int v = (int)(idx / ws.n);
     const uint32_t i = (uint32_t)(idx - (int64_t)v * ws.n);
-    const int4 rc = ws.rec.c[idx];
-    const uint32_t dbits = __float_as_uint(ws.rec.b[idx].w);
+    const int4 rc = ws.rec[idx].c;
+    const uint32_t dbits = __float_as_uint(ws.rec[idx].b.w);
     const xg_camera &c = cams[v];
     const int txn = (c.width + tile - 1) / tile;
     const int tx0 = (rc.z & 0xffff) / tile, tx1 = (rc.z >> 16) / tile;
@@ -279,8 +283,12 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
 }
 
 // Adjoint of the projection for one Gaussian, summed over views.
-// grad2d per (view, Gaussian): (dL/du_x, dL/du_y, dL/dA, dL/dB, dL/dC,
-// dL/do, dL/di, 0) with the inverse covariance [[A, B], [B, C]].
+// grad2d per (view, Gaussian) holds pixel sums of g_p = dL/dpower_p times
+// the offsets d = pixel centre - u:
+//   (sum g dx, sum g dy, sum g dx^2, sum g dx dy, sum g dy^2, dL/do, dL/di, 0)
+// With power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 and [[A, B], [B, C]] the
+// inverse 2-D covariance: dL/du = [[A, B], [B, C]] (sum g d),
+// dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy, dL/dC = -sum g dy^2 / 2.
 __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
                                                         Params p, xg_grads gr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,8 +314,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         for (int k = 0; k < 9; ++k) r[k] = (double)c.rot[k];
         const double det = P.sxx * P.syy - P.sxy * P.sxy;
         const double QA = P.syy / det, QB = -P.sxy / det, QC = P.sxx / det;
+        const double gux = QA * (double)g0.x + QB * (double)g0.y;
+        const double guy = QB * (double)g0.x + QC * (double)g0.y;
         // dL/dSigma'' = -Q G_Q Q, off-diagonal of G_Q carrying half of dL/dB
-        const double gA = g0.z, gB = 0.5 * (double)g0.w, gC = g1.x;
+        const double gA = -0.5 * (double)g0.z, gB = -0.5 * (double)g0.w, gC = -0.5 * (double)g1.x;
         const double T00 = gA * QA + gB * QB, T01 = gA * QB + gB * QC;
         const double T10 = gB * QA + gC * QB, T11 = gB * QB + gC * QC;
         const double GS00 = -(QA * T00 + QB * T10);
@@ -365,7 +375,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         const double GJ12 = GA2[3] * r[6] + GA2[4] * r[7] + GA2[5] * r[8];
         const double fx = c.fx, fy = c.fy, tx = P.t[0], ty = P.t[1], tz = P.t[2];
         const double tz2 = tz * tz, tz3 = tz2 * tz;
-        const double gux = g0.x, guy = g0.y;
         const double gtx = GJ02 * (-fx / tz2) + gux * (fx / tz);
         const double gty = GJ12 * (-fy / tz2) + guy * (fy / tz);
         const double gtz = GJ00 * (-fx / tz2) + GJ02 * (2.0 * fx * tx / tz3)

@@ -67,17 +67,32 @@ __device__ __forceinline__ TileGeom tile_geom(const xg_camera *cams, int n_views
     return t;
 }
 
-// Stages list entries [b0, b0 + cnt) of the tile into LDS.
+// Bit s of the result: the tile-local rectangle [xl, xh] x [yl, yh] touches
+// the 8 x 8 sub-block s (row-major, SB sub-blocks per row).
+template <int SB>
+__device__ __forceinline__ uint32_t subblock_mask(int xl, int xh, int yl, int yh) {
+    const int cx0 = xl >> 3, cx1 = xh >> 3, cy0 = yl >> 3, cy1 = yh >> 3;
+    const uint32_t row = ((1u << (cx1 - cx0 + 1)) - 1u) << cx0;
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < SB; ++r)
+        if (r >= cy0 && r <= cy1) m |= row << (r * SB);
+    return m;
+}
+
+// Stages list entries [b0, b0 + cnt) of the tile into LDS, with the mask of
+// the 8 x 8 sub-blocks each entry's rectangle touches.
 template <int T, int NT>
 __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32_t b0, int cnt,
                                       const TileGeom &tg, float4 *s_a, float4 *s_b,
-                                      uint32_t *s_rid) {
+                                      uint16_t *s_mask, uint32_t *s_rid) {
     for (int k = threadIdx.x; k < cnt; k += NT) {
         const uint32_t gi = vals[b0 + k];
         const int64_t rid = (int64_t)tg.view * ws.n + gi;
-        const float4 ra = ws.rec.a[rid];
-        const float4 rb = ws.rec.b[rid];
-        const int4 rc = ws.rec.c[rid];
+        const Record &rec = ws.rec[rid];
+        const float4 ra = rec.a;
+        const float4 rb = rec.b;
+        const int4 rc = rec.c;
         const float ux = (float)(rc.x - tg.rx) + ra.x;
         const float uy = (float)(rc.y - tg.ry) + ra.y;
         const int xl = max((rc.z & 0xffff) - tg.x0, 0), xh = min((rc.z >> 16) - tg.x0, T - 1);
@@ -85,23 +100,54 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         const uint32_t rect = (uint32_t)xl | ((uint32_t)xh << 8) | ((uint32_t)yl << 16) | ((uint32_t)yh << 24);
         s_a[k] = make_float4(ux, uy, ra.z, ra.w);
         s_b[k] = make_float4(rb.x, rb.y, rb.z, __uint_as_float(rect));
+        if (T > 8) s_mask[k] = (uint16_t)subblock_mask<T / 8>(xl, xh, yl, yh);
         if (s_rid) s_rid[k] = (uint32_t)rid;
     }
 }
 
-// COUNT = true: instead of the image, write the per-pixel work counts
-// (evaluations, contributors, evaluations up to the last contributor) into
-// counts[3][total pixels]; the blending decisions are the same.
-template <int T, int B, bool COUNT>
-__global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *cams, Params p,
-                                                      float *image, float *final_t,
-                                                      int32_t *n_contrib, int32_t *counts) {
-    constexpr int NT = T * T;
-    constexpr int SB = T / 8;
-    __shared__ float4 s_a[B];
-    __shared__ float4 s_b[B];
+// Compacts, in list order, the staged entries [0, cnt) whose rectangle
+// touches this wavefront's sub-block w into list[]; returns their number
+// (wavefront-uniform).  A tile of one 8 x 8 block needs no list.
+template <int NW>
+__device__ __forceinline__ int wave_list(const uint16_t *s_mask, int cnt, int w, uint16_t *list) {
+    if (NW == 1) return cnt;
+    const int lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int n = 0;
+    for (int c = 0; c < cnt; c += kWave) {
+        const int k = c + lane;
+        const bool sel = k < cnt && ((s_mask[k] >> w) & 1u);
+        const uint64_t bal = __ballot(sel);
+        if (sel) list[n + __popcll(bal & lt)] = (uint16_t)k;
+        n += __popcll(bal);
+    }
+    return n;
+}
 
-    const int tile = blockIdx.x;
+// LDS of one blending workgroup (the forward leaves rid and wmax unused).
+template <int T, int B>
+struct BlendLds {
+    static constexpr int NW = T * T / kWave;
+    float4 a[B];
+    float4 b[B];
+    uint32_t rid[B];
+    uint16_t mask[T > 8 ? B : 1];
+    uint16_t list[NW > 1 ? NW : 1][NW > 1 ? B : 1];
+    int wmax[NW];
+    int next;
+};
+
+template <int T, int B, bool COUNT>
+__device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera *cams,
+                                         const Params &p, float *image, float *final_t,
+                                         int32_t *n_contrib, int32_t *counts, BlendLds<T, B> &sh) {
+    constexpr int NT = T * T;
+    constexpr int NW = NT / kWave;
+    constexpr int SB = T / 8;
+    float4 *s_a = sh.a;
+    float4 *s_b = sh.b;
+    uint16_t *s_mask = sh.mask;
+
     const TileGeom tg = tile_geom(cams, ws.n_views, tile, T);
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -116,6 +162,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *ca
     const uint32_t e = ws.ranges[2 * (int64_t)tile + 1];
     const uint32_t *vals = ws.values[ws.hdr->sort_sel & 1];
     const float amin = p.alpha_min, amax = p.alpha_max, tmin = p.t_min;
+    uint16_t *list = sh.list[NW > 1 ? w : 0];
 
     float Tr = 1.0f, C = 0.0f;
     int last = 0;
@@ -124,34 +171,41 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *ca
     for (uint32_t b0 = s; b0 < e; b0 += B) {
         const int cnt = (int)min((uint32_t)B, e - b0);
         if (!__syncthreads_or(!done)) break;
-        stage<T, NT>(ws, vals, b0, cnt, tg, s_a, s_b, nullptr);
+        stage<T, NT>(ws, vals, b0, cnt, tg, s_a, s_b, s_mask, nullptr);
         __syncthreads();
-        if (__any(!done)) {
-            for (int k = 0; k < cnt; ++k) {
-                const float4 sa = s_a[k];
-                const float4 sb = s_b[k];
-                const uint32_t rect = __builtin_amdgcn_readfirstlane(__float_as_uint(sb.w));
-                const int rxl = rect & 255, rxh = (rect >> 8) & 255;
-                const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-                if (rxh < sx || rxl > sx + 7 || ryh < sy || ryl > sy + 7) continue;
-                const bool inr = lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
-                if (!done && inr) {
-                    const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
-                    if (COUNT) ++n_eval;
-                    if (ev.alpha >= amin) {
-                        const float Tn = Tr * (1.0f - ev.alpha);
-                        if (Tn < tmin) {
-                            done = true;
-                        } else {
-                            C = fmaf(sb.z * ev.alpha, Tr, C);
-                            Tr = Tn;
-                            last = (int)(b0 - s) + k + 1;
-                            if (COUNT) { ++n_con; n_upto = n_eval; }
-                        }
-                    }
-                }
-                if (!__any(!done)) break;
+        if (!__any(!done)) continue;
+        const int nl = wave_list<NW>(s_mask, cnt, w, list);
+        if (nl == 0) continue;
+        int kn = (NW > 1) ? (int)list[0] : 0;
+        float4 na = s_a[kn], nb = s_b[kn];
+        for (int j = 0; j < nl; ++j) {
+            // the next entry's loads are issued before this entry's math
+            const int k = kn;
+            const float4 sa = na, sb = nb;
+            if (j + 1 < nl) {
+                kn = (NW > 1) ? (int)list[j + 1] : j + 1;
+                na = s_a[kn];
+                nb = s_b[kn];
             }
+            const uint32_t rect = __float_as_uint(sb.w);
+            const int rxl = rect & 255, rxh = (rect >> 8) & 255;
+            const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
+            const bool act = !done && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
+            const bool con = act && ev.alpha >= amin;
+            const float Tn = Tr * (1.0f - ev.alpha);
+            const bool term = con && Tn < tmin;
+            const bool keep = con && !term;
+            done = done || term;
+            C = keep ? fmaf(sb.z * ev.alpha, Tr, C) : C;
+            Tr = keep ? Tn : Tr;
+            last = keep ? (int)(b0 - s) + k + 1 : last;
+            if (COUNT) {
+                n_eval += act ? 1 : 0;
+                n_con += keep ? 1 : 0;
+                n_upto = keep ? n_eval : n_upto;
+            }
+            if (!__any(!done)) break;
         }
     }
     if (inside) {
@@ -168,50 +222,106 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *ca
     }
 }
 
-// Sum of 8 per-lane values over the wavefront, transposed: afterwards the
-// lanes whose bits 0..2 are zero hold the total of value q = lane >> 3.
+// Pops the next tile of the heavy-first work order (-1 when exhausted).
+template <int T, int B>
+__device__ __forceinline__ int pop_tile(const Ws &ws, int32_t *queue, BlendLds<T, B> &sh) {
+    if (threadIdx.x == 0) {
+        const int q = atomicAdd(queue, 1);
+        sh.next = q < ws.total_tiles ? ws.tile_order[q] : -1;
+    }
+    __syncthreads();
+    const int t = sh.next;
+    __syncthreads();
+    return t;
+}
+
+// The last workgroup of a persistent launch to finish rewinds the queue, so
+// the next launch on this workspace starts from the first tile again.
+__device__ __forceinline__ void finish_queue(int32_t *queue, int32_t *done) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(done, 1) == (int)gridDim.x - 1) {
+            atomicExch(queue, 0);
+            atomicExch(done, 0);
+        }
+    }
+}
+
+// COUNT = true: instead of the image, write the per-pixel work counts
+// (evaluations, contributors, evaluations up to the last contributor) into
+// counts[3][total pixels]; the blending decisions are the same.
+// PERSIST = true: a grid sized to the device's resident capacity takes
+// tiles from the work queue; otherwise one workgroup per tile.
+template <int T, int B, bool COUNT, bool PERSIST>
+__global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *cams, Params p,
+                                                      float *image, float *final_t,
+                                                      int32_t *n_contrib, int32_t *counts) {
+    __shared__ BlendLds<T, B> sh;
+    if (!PERSIST) {
+        fwd_tile<T, B, COUNT>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image, final_t, n_contrib, counts, sh);
+        return;
+    }
+    for (;;) {
+        const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_fwd, sh);
+        if (tile < 0) break;
+        fwd_tile<T, B, COUNT>(tile, ws, cams, p, image, final_t, n_contrib, counts, sh);
+    }
+    finish_queue(&ws.hdr->queue_fwd, &ws.hdr->done_fwd);
+}
+
+// DPP lane permutations (row = 16 lanes): quad xor 1, quad xor 2, lane
+// i^8 within a row (rotate by 8), and mirror within each half row.
+#define XG_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRowRor8 = 0x128;   // row_ror:8
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+
+// Sum of 8 per-lane values over the wavefront, transposed so that every
+// step halves the number of live values: afterwards the lanes whose bits
+// 0..2 are zero hold the total of value q = lane >> 3.  All steps are VALU
+// (gfx950 permlane swaps and DPP), no LDS traffic: 18 instructions.
 __device__ __forceinline__ float wave_reduce8(float v[8]) {
     const int lane = lane_id();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const bool hi = lane & 32;
-        const float send = hi ? v[k] : v[k + 4];
-        const float keep = hi ? v[k + 4] : v[k];
-        v[k] = keep + __shfl_xor(send, 32, kWave);
+        // lanes 0-31 end with value k summed over lane pairs (l, l+32),
+        // lanes 32-63 with value k+4
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 4]),
+                                                        false, false);
+        v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        const bool hi = lane & 16;
-        const float send = hi ? v[k] : v[k + 2];
-        const float keep = hi ? v[k + 2] : v[k];
-        v[k] = keep + __shfl_xor(send, 16, kWave);
+        // within each half: even rows keep value k, odd rows value k+2
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 2]),
+                                                        false, false);
+        v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    {
-        const bool hi = lane & 8;
-        const float send = hi ? v[0] : v[1];
-        const float keep = hi ? v[1] : v[0];
-        v[0] = keep + __shfl_xor(send, 8, kWave);
-    }
-    float x = v[0];
-    x += __shfl_xor(x, 4, kWave);
-    x += __shfl_xor(x, 2, kWave);
-    x += __shfl_xor(x, 1, kWave);
+    const bool hi = lane & 8;
+    const float mine = hi ? v[1] : v[0];
+    const float other = hi ? v[0] : v[1];
+    float x = mine + XG_DPP(other, kDppRowRor8);
+    x += XG_DPP(x, kDppQuadXor1);
+    x += XG_DPP(x, kDppQuadXor2);
+    x += XG_DPP(x, kDppHalfMirror);
     return x;
 }
 
 template <int T, int B>
-__global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *cams, Params p,
-                                                      const float *dl_dimage, const float *final_t,
-                                                      const int32_t *n_contrib) {
+__device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera *cams,
+                                         const Params &p, const float *dl_dimage,
+                                         const float *final_t, const int32_t *n_contrib,
+                                         BlendLds<T, B> &sh) {
     constexpr int NT = T * T;
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
-    __shared__ float4 s_a[B];
-    __shared__ float4 s_b[B];
-    __shared__ uint32_t s_rid[B];
-    __shared__ int s_max[NW];
+    float4 *s_a = sh.a;
+    float4 *s_b = sh.b;
+    uint32_t *s_rid = sh.rid;
+    uint16_t *s_mask = sh.mask;
+    int *s_max = sh.wmax;
 
-    const int tile = blockIdx.x;
     const TileGeom tg = tile_geom(cams, ws.n_views, tile, T);
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -225,6 +335,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *ca
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
     const uint32_t *vals = ws.values[ws.hdr->sort_sel & 1];
     const float amin = p.alpha_min, amax = p.alpha_max;
+    uint16_t *list = sh.list[NW > 1 ? w : 0];
 
     float g = 0.0f, Tr = 1.0f;
     int last = 0;
@@ -250,17 +361,28 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *ca
         const int b0 = max(end - B, 0);
         const int cnt = end - b0;
         __syncthreads();
-        stage<T, NT>(ws, vals, s + (uint32_t)b0, cnt, tg, s_a, s_b, s_rid);
+        stage<T, NT>(ws, vals, s + (uint32_t)b0, cnt, tg, s_a, s_b, s_mask, s_rid);
         __syncthreads();
         if (b0 >= wmax) continue;
-        for (int k = min(cnt, wmax - b0) - 1; k >= 0; --k) {
+        const int nl = wave_list<NW>(s_mask, min(cnt, wmax - b0), w, list);
+        if (nl == 0) continue;
+        int kn = (NW > 1) ? (int)list[nl - 1] : nl - 1;
+        float4 na = s_a[kn], nb = s_b[kn];
+        uint32_t nr = s_rid[kn];
+        for (int j = nl - 1; j >= 0; --j) {
+            const int k = kn;
+            const float4 sa = na, sb = nb;
+            const uint32_t rid = nr;
+            if (j > 0) {
+                kn = (NW > 1) ? (int)list[j - 1] : j - 1;
+                na = s_a[kn];
+                nb = s_b[kn];
+                nr = s_rid[kn];
+            }
             const int pos1 = b0 + k + 1;
-            const float4 sa = s_a[k];
-            const float4 sb = s_b[k];
-            const uint32_t rect = __builtin_amdgcn_readfirstlane(__float_as_uint(sb.w));
+            const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            if (rxh < sx || rxl > sx + 7 || ryh < sy || ryl > sy + 7) continue;
             const bool inr = lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
             float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             bool act = false;
@@ -269,36 +391,75 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *ca
                 if (ev.alpha >= amin) {
                     act = true;
                     const float om = 1.0f - ev.alpha;
-                    Tr = Tr / om;                           // transmittance before this Gaussian
+                    Tr = Tr * __builtin_amdgcn_rcpf(om);    // transmittance before this Gaussian
                     const float it = sb.z;
-                    v[6] = g * ev.alpha * Tr;               // dL/d intensity
-                    const float galpha = g * Tr * (it - R); // dL/d alpha
+                    const float gT = g * Tr;
+                    v[6] = gT * ev.alpha;                   // dL/d intensity
+                    const float galpha = gT * (it - R);     // dL/d alpha
                     R = fmaf(it, ev.alpha, om * R);
                     const float ga = (ev.a > amax) ? 0.0f : galpha;
                     v[5] = ga * ev.G;                       // dL/d opacity
-                    const float gp = ga * ev.a;             // dL/d power (natural log)
-                    const float gk = gp * kInvLog2eHalf;
-                    v[0] = gk * (ev.y1 * sa.z);                      // dL/du_x
-                    v[1] = gk * fmaf(ev.y1, sa.w, ev.y2 * sb.x);     // dL/du_y
-                    v[2] = -0.5f * gp * ev.dx * ev.dx;               // dL/dA
-                    v[3] = -gp * ev.dx * ev.dy;                      // dL/dB
-                    v[4] = -0.5f * gp * ev.dy * ev.dy;               // dL/dC
+                    const float gp = ga * ev.a;             // dL/d power, power = -d^T Q d / 2
+                    // moments of gp over the pixel offsets d = pixel - u; the
+                    // inverse covariance is applied once per (view, Gaussian)
+                    v[0] = gp * ev.dx;
+                    v[1] = gp * ev.dy;
+                    v[2] = v[0] * ev.dx;
+                    v[3] = v[0] * ev.dy;
+                    v[4] = v[1] * ev.dy;
                 }
             }
             if (!__any(act)) continue;
             const float x = wave_reduce8(v);
             const int q = lane >> 3;
-            if ((lane & 7) == 0 && q < 7) atomicAdd(&g2d[8 * (int64_t)s_rid[k] + q], x);
+            if ((lane & 7) == 0 && q < 7) atomicAdd(&g2d[8 * (int64_t)rid + q], x);
         }
     }
 }
 
+template <int T, int B, bool PERSIST>
+__global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *cams, Params p,
+                                                      const float *dl_dimage, const float *final_t,
+                                                      const int32_t *n_contrib) {
+    __shared__ BlendLds<T, B> sh;
+    if (!PERSIST) {
+        bwd_tile<T, B>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, dl_dimage, final_t, n_contrib, sh);
+        return;
+    }
+    for (;;) {
+        const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_bwd, sh);
+        if (tile < 0) break;
+        bwd_tile<T, B>(tile, ws, cams, p, dl_dimage, final_t, n_contrib, sh);
+        __syncthreads();
+    }
+    finish_queue(&ws.hdr->queue_bwd, &ws.hdr->done_bwd);
+}
+
+// Workgroups of `kernel` that fit on the device at once (persistent grid).
+template <typename K>
+unsigned resident_grid(K kernel, int threads, int64_t work) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) return 0;
+    int64_t g = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+    if (g > work) g = work;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
 template <int T, int B>
 hipError_t fwd_t(const Ws &ws, const xg_camera *cams, const Params &p, float *image, float *final_t,
-                 int32_t *n_contrib, hipStream_t st) {
-    const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
-    hipLaunchKernelGGL((k_render_fwd<T, B, false>), dim3(nb), dim3(T * T), 0, st, ws, cams, p, image,
-                       final_t, n_contrib, nullptr);
+                 int32_t *n_contrib, int persistent, hipStream_t st) {
+    if (persistent) {
+        const unsigned g = resident_grid(k_render_fwd<T, B, false, true>, T * T, ws.total_tiles);
+        if (g == 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_render_fwd<T, B, false, true>), dim3(g), dim3(T * T), 0, st, ws, cams, p,
+                           image, final_t, n_contrib, nullptr);
+    } else {
+        const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
+        hipLaunchKernelGGL((k_render_fwd<T, B, false, false>), dim3(nb), dim3(T * T), 0, st, ws, cams,
+                           p, image, final_t, n_contrib, nullptr);
+    }
     return hipGetLastError();
 }
 
@@ -306,17 +467,24 @@ template <int T, int B>
 hipError_t counts_t(const Ws &ws, const xg_camera *cams, const Params &p, int32_t *counts,
                     hipStream_t st) {
     const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
-    hipLaunchKernelGGL((k_render_fwd<T, B, true>), dim3(nb), dim3(T * T), 0, st, ws, cams, p, nullptr,
-                       nullptr, nullptr, counts);
+    hipLaunchKernelGGL((k_render_fwd<T, B, true, false>), dim3(nb), dim3(T * T), 0, st, ws, cams, p,
+                       nullptr, nullptr, nullptr, counts);
     return hipGetLastError();
 }
 
 template <int T, int B>
 hipError_t bwd_t(const Ws &ws, const xg_camera *cams, const Params &p, const float *dl,
-                 const float *final_t, const int32_t *n_contrib, hipStream_t st) {
-    const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
-    hipLaunchKernelGGL((k_render_bwd<T, B>), dim3(nb), dim3(T * T), 0, st, ws, cams, p, dl, final_t,
-                       n_contrib);
+                 const float *final_t, const int32_t *n_contrib, int persistent, hipStream_t st) {
+    if (persistent) {
+        const unsigned g = resident_grid(k_render_bwd<T, B, true>, T * T, ws.total_tiles);
+        if (g == 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_render_bwd<T, B, true>), dim3(g), dim3(T * T), 0, st, ws, cams, p, dl,
+                           final_t, n_contrib);
+    } else {
+        const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
+        hipLaunchKernelGGL((k_render_bwd<T, B, false>), dim3(nb), dim3(T * T), 0, st, ws, cams, p, dl,
+                           final_t, n_contrib);
+    }
     return hipGetLastError();
 }
 
@@ -338,15 +506,13 @@ hipError_t bwd_t(const Ws &ws, const xg_camera *cams, const Params &p, const flo
 
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p, float *image,
                              float *final_t, int32_t *n_contrib, int persistent, hipStream_t s) {
-    (void)persistent;
-    XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, s)
+    XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, persistent, s)
 }
 
 hipError_t launch_render_bwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              const float *dl_dimage, const float *final_t,
                              const int32_t *n_contrib, int persistent, hipStream_t s) {
-    (void)persistent;
-    XG_DISPATCH(bwd_t, ws, cams, p, dl_dimage, final_t, n_contrib, s)
+    XG_DISPATCH(bwd_t, ws, cams, p, dl_dimage, final_t, n_contrib, persistent, s)
 }
 
 hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Params &p,

@@ -166,7 +166,43 @@ __global__ __launch_bounds__(256) void k_ranges(Ws ws) {
     }
 }
 
+// Work order for the persistent blending kernels: tiles bucketed by list
+// length on a logarithmic scale (8 buckets per octave), longest first, so
+// the heaviest tiles start early and the tail of the launch stays short.
+// One workgroup; the order inside a bucket is arbitrary (it only affects
+// scheduling, not results).
+constexpr int kOrderBuckets = 256;
+
+__global__ __launch_bounds__(1024) void k_tile_order(Ws ws) {
+    __shared__ uint32_t hist[kOrderBuckets];
+    __shared__ uint32_t scan_lds[1024 / kWave + 1];
+    const int64_t nt = ws.total_tiles;
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    auto key = [&](int64_t t) -> int {
+        const uint32_t len = ws.ranges[2 * t + 1] - ws.ranges[2 * t];
+        const int l = (int)(8.0f * __log2f((float)len + 1.0f));
+        return kOrderBuckets - 1 - min(l, kOrderBuckets - 1);
+    };
+    for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) atomicAdd(&hist[key(t)], 1u);
+    __syncthreads();
+    const uint32_t v = threadIdx.x < kOrderBuckets ? hist[threadIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, scan_lds, &tot);
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = ex;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) {
+        const uint32_t pos = atomicAdd(&hist[key(t)], 1u);
+        ws.tile_order[pos] = (int32_t)t;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_tile_order(const Ws &ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ws);
+    return hipGetLastError();
+}
 
 hipError_t launch_sort(const Ws &ws, hipStream_t s) {
     const int passes = (ws.tile_bits + 32 + kRadixBits - 1) / kRadixBits;

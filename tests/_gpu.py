@@ -27,13 +27,14 @@ def oracle_cams(angles, sizes):
 
 
 def gpu_run(g: dict, angles, sizes, tile=16, lds=256, upstream=None, cap=None, lowpass=0.3,
-            alpha_min=1.0 / 255.0, t_min=1e-4, backward=True):
+            alpha_min=1.0 / 255.0, t_min=1e-4, backward=True, persistent=False):
     """Forward (and optionally backward) on cuda:0 through the C ABI."""
     import torch
     import paper_2403_04116_amd as P
     dev = torch.device("cuda:0")
     cams = P.cameras(angles, sizes, S.L_SO, S.L_SD, D, D)
-    st = P.settings(tile=tile, lds_batch=lds, lowpass=lowpass, alpha_min=alpha_min, t_min=t_min)
+    st = P.settings(tile=tile, lds_batch=lds, lowpass=lowpass, alpha_min=alpha_min, t_min=t_min,
+                    persistent=persistent)
     n = g["means"].shape[0]
     frame = P.Frame(n, cams, st, pair_capacity=cap, device=dev)
     gt = {k: torch.from_numpy(np.ascontiguousarray(g[k])).to(dev) for k in KEYS}
