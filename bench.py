@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds", type=int, default=256)
-    ap.add_argument("--persistent", type=int, default=1, help="persistent blending kernels (1/0)")
+    ap.add_argument("--persistent", type=int, default=0, help="persistent blending kernels (1/0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)

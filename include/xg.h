@@ -70,7 +70,7 @@ typedef struct {
     int32_t lds_batch;     /* 64 | 128 | 256 Gaussians staged in LDS at once */
     float lowpass;         /* k of Sigma'' + k I (>= 0)                       */
     float alpha_min;       /* skip an evaluation with alpha < alpha_min      */
-    float alpha_max;       /* clamp alpha to alpha_max                        */
+    float alpha_max;       /* clamp alpha to alpha_max (< 1)                  */
     float t_min;           /* stop before transmittance drops below t_min    */
     float near_z;          /* cull Gaussians with camera depth <= near_z     */
     uint32_t flags;        /* XG_F_* bits                                     */

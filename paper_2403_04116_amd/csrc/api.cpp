@@ -22,7 +22,8 @@ bool valid_settings(const xg_settings &s) {
     if (s.lds_batch != 64 && s.lds_batch != 128 && s.lds_batch != 256) return false;
     if (!(s.lowpass >= 0.0f) || !isfinite(s.lowpass)) return false;
     if (!(s.alpha_min >= 0.0f && s.alpha_min < 1.0f)) return false;
-    if (!(s.alpha_max > 0.0f && s.alpha_max <= 1.0f)) return false;
+    // the backward recovers the transmittance by dividing by 1 - alpha
+    if (!(s.alpha_max > 0.0f && s.alpha_max < 1.0f)) return false;
     if (!(s.alpha_min <= s.alpha_max)) return false;
     if (!(s.t_min >= 0.0f && s.t_min < 1.0f)) return false;
     if (!isfinite(s.near_z)) return false;

@@ -175,18 +175,10 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (!__any(!done)) continue;
         const int nl = wave_list<NW>(s_mask, cnt, w, list);
-        if (nl == 0) continue;
-        int kn = (NW > 1) ? (int)list[0] : 0;
-        float4 na = s_a[kn], nb = s_b[kn];
         for (int j = 0; j < nl; ++j) {
-            // the next entry's loads are issued before this entry's math
-            const int k = kn;
-            const float4 sa = na, sb = nb;
-            if (j + 1 < nl) {
-                kn = (NW > 1) ? (int)list[j + 1] : j + 1;
-                na = s_a[kn];
-                nb = s_b[kn];
-            }
+            const int k = (NW > 1) ? (int)list[j] : j;
+            const float4 sa = s_a[k];
+            const float4 sb = s_b[k];
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
@@ -205,7 +197,8 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 n_con += keep ? 1 : 0;
                 n_upto = keep ? n_eval : n_upto;
             }
-            if (!__any(!done)) break;
+            // leave the batch once every lane of the wavefront has terminated
+            if ((j & 7) == 7 && !__any(!done)) break;
         }
     }
     if (inside) {
@@ -365,54 +358,45 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (b0 >= wmax) continue;
         const int nl = wave_list<NW>(s_mask, min(cnt, wmax - b0), w, list);
-        if (nl == 0) continue;
-        int kn = (NW > 1) ? (int)list[nl - 1] : nl - 1;
-        float4 na = s_a[kn], nb = s_b[kn];
-        uint32_t nr = s_rid[kn];
         for (int j = nl - 1; j >= 0; --j) {
-            const int k = kn;
-            const float4 sa = na, sb = nb;
-            const uint32_t rid = nr;
-            if (j > 0) {
-                kn = (NW > 1) ? (int)list[j - 1] : j - 1;
-                na = s_a[kn];
-                nb = s_b[kn];
-                nr = s_rid[kn];
-            }
+            const int k = (NW > 1) ? (int)list[j] : j;
+            const float4 sa = s_a[k];
+            const float4 sb = s_b[k];
             const int pos1 = b0 + k + 1;
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            const bool inr = lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
-            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            bool act = false;
-            if (pos1 <= last && inr) {
-                const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
-                if (ev.alpha >= amin) {
-                    act = true;
-                    const float om = 1.0f - ev.alpha;
-                    Tr = Tr * __builtin_amdgcn_rcpf(om);    // transmittance before this Gaussian
-                    const float it = sb.z;
-                    const float gT = g * Tr;
-                    v[6] = gT * ev.alpha;                   // dL/d intensity
-                    const float galpha = gT * (it - R);     // dL/d alpha
-                    R = fmaf(it, ev.alpha, om * R);
-                    const float ga = (ev.a > amax) ? 0.0f : galpha;
-                    v[5] = ga * ev.G;                       // dL/d opacity
-                    const float gp = ga * ev.a;             // dL/d power, power = -d^T Q d / 2
-                    // moments of gp over the pixel offsets d = pixel - u; the
-                    // inverse covariance is applied once per (view, Gaussian)
-                    v[0] = gp * ev.dx;
-                    v[1] = gp * ev.dy;
-                    v[2] = v[0] * ev.dx;
-                    v[3] = v[0] * ev.dy;
-                    v[4] = v[1] * ev.dy;
-                }
-            }
+            const bool inr = pos1 <= last && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
+            const bool act = inr && ev.alpha >= amin;
             if (!__any(act)) continue;
+            // Every lane runs the same arithmetic; a lane that is not a
+            // contributor gets a zero upstream gradient (exact zeros in the
+            // reduction) and keeps its transmittance and R.
+            const float om = 1.0f - ev.alpha;
+            const float Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;   // T before this Gaussian
+            const float ge = act ? g : 0.0f;
+            const float it = sb.z;
+            const float gT = ge * Tj;
+            float v[8];
+            v[6] = gT * ev.alpha;                          // dL/d intensity
+            const float galpha = gT * (it - R);            // dL/d alpha
+            R = act ? fmaf(it, ev.alpha, om * R) : R;
+            Tr = Tj;
+            const float ga = (ev.a > amax) ? 0.0f : galpha;
+            v[5] = ga * ev.G;                              // dL/d opacity
+            const float gp = ga * ev.a;                    // dL/d power, power = -d^T Q d / 2
+            // moments of gp over the pixel offsets d = pixel - u; the inverse
+            // covariance is applied once per (view, Gaussian)
+            v[0] = gp * ev.dx;
+            v[1] = gp * ev.dy;
+            v[2] = v[0] * ev.dx;
+            v[3] = v[0] * ev.dy;
+            v[4] = v[1] * ev.dy;
+            v[7] = 0.0f;
             const float x = wave_reduce8(v);
             const int q = lane >> 3;
-            if ((lane & 7) == 0 && q < 7) atomicAdd(&g2d[8 * (int64_t)rid + q], x);
+            if ((lane & 7) == 0 && q < 7) atomicAdd(&g2d[8 * (int64_t)s_rid[k] + q], x);
         }
     }
 }

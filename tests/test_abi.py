@@ -97,7 +97,8 @@ def test_workspace_size_grows_with_capacity_and_views():
 
 @pytest.mark.parametrize("field,value", [
     ("tile", 12), ("lds_batch", 100), ("lowpass", -1.0), ("alpha_min", 1.0),
-    ("alpha_max", 0.0), ("t_min", 1.0), ("near_z", float("nan")), ("flags", 8)])
+    ("alpha_max", 0.0), ("alpha_max", 1.0), ("t_min", 1.0), ("near_z", float("nan")),
+    ("flags", 8)])
 def test_invalid_settings_rejected(field, value):
     f, _ = _frame(**{field: value})
     with pytest.raises(X.XgError) as e:
