@@ -108,17 +108,21 @@ typedef struct {
     int64_t pair_capacity;      /* 0 < pair_capacity < 2^31 */
 } xg_frame;
 
-/* Workspace sub-buffer offsets (bytes from ws), for inspection and tests. */
+/* Workspace sub-buffer offsets (bytes from ws), for inspection and tests.
+ * The sorted lists are stored as parallel arrays: pair p of the sorted
+ * order has global tile id pair_tiles[p] and Gaussian index pair_values[p];
+ * its sort key is (pair_tiles[p] << 32) | float32 bits of the camera depth
+ * of (view of that tile, Gaussian pair_values[p]), which is word 7 of that
+ * (view, Gaussian)'s 64-byte render record. */
 typedef struct {
     size_t status;      /* int32: XG_OK or XG_ECAPACITY                       */
     size_t n_pairs;     /* int32: pairs emitted (may exceed the capacity)     */
-    size_t sort_sel;    /* int32: 0 -> keys0/values0 hold the sorted pairs, 1 -> keys1/values1 */
     size_t depth_range; /* uint32[2]: min and max depth bits of kept Gaussians */
     size_t records;     /* 64-byte render records per (view, Gaussian)        */
     size_t counts;      /* uint32[n_views*n]: tiles touched (0 = culled)      */
-    size_t offsets;     /* uint32[n_views*n]: exclusive scan of counts        */
-    size_t keys0, keys1;     /* uint64[pair_capacity]                         */
-    size_t values0, values1; /* uint32[pair_capacity]                         */
+    size_t offsets;     /* uint32[n_views*n]: scan of counts in depth order   */
+    size_t pair_tiles;  /* uint32[pair_capacity]: tile ids, sorted            */
+    size_t pair_values; /* uint32[pair_capacity]: Gaussian indices, sorted    */
     size_t ranges;      /* uint32[total_tiles][2]: [start, end) per tile      */
     size_t grad2d;      /* float[n_views*n][8]: per-view 2-D gradients        */
     size_t total;       /* bytes needed                                       */
@@ -173,12 +177,14 @@ xg_status xg_workspace_size(const xg_frame *f /* [host] */, size_t *bytes /* [ho
 xg_status xg_preprocess(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                         void *stream);
 
-/* Stage 2 (Sec. 3.2): exclusive scan of the tile counts, emission of one
- * (key, value) pair per (view, Gaussian, tile) with
- * key = (global tile id << 32) | float32 bits of the camera depth and
- * value = Gaussian index, a stable ascending radix sort of the pairs on the
- * key bits that vary, and per-tile [start, end) ranges.  Equal keys keep
- * ascending Gaussian index. */
+/* Stage 2 (Sec. 3.2): the per-tile lists of Gaussians sorted by camera
+ * depth.  The (view, Gaussian) items are radix-sorted stably by (view,
+ * depth) on the depth bits that vary; their tile counts are scanned in
+ * that order; one (global tile id, Gaussian index) pair is emitted per
+ * (view, Gaussian, tile) in that order; and the pairs are radix-sorted
+ * stably by tile id.  The result equals a sort of the keys
+ * (tile << 32 | float32 bits of the depth), ties by ascending Gaussian
+ * index.  Also fills per-tile [start, end) ranges. */
 xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
 
 /* Stage 3 (Eq. 10): front-to-back blending of every pixel over its tile's

@@ -65,8 +65,8 @@ class XgFrame(C.Structure):
 
 class XgWsLayout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in (
-        "status", "n_pairs", "sort_sel", "depth_range", "records", "counts", "offsets",
-        "keys0", "keys1", "values0", "values1", "ranges", "grad2d", "total")]
+        "status", "n_pairs", "depth_range", "records", "counts", "offsets", "pair_tiles",
+        "pair_values", "ranges", "grad2d", "total")]
 
 
 if not os.path.exists(LIB_PATH):

@@ -68,10 +68,12 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 
 struct Plan {
     xg_ws_layout lay;
-    size_t depth_part, scan_tmp, hist, hist_tmp, tile_order;
+    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], hist, hist_tmp, tile_order;
     int64_t total_px, total_tiles, n_items;
-    int32_t hist_blocks;
+    int32_t item_blocks, pair_blocks, tile_bits, view_bits, pair_passes;
 };
+
+int bits_of(int64_t v) { return v <= 0 ? 0 : 64 - __builtin_clzll((unsigned long long)v); }
 
 xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     xg_status st = check_frame(f, need_ws, &P.total_px, &P.total_tiles);
@@ -79,8 +81,12 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     const int64_t ni = (int64_t)f->n * f->n_views;
     const int64_t cap = f->pair_capacity;
     P.n_items = ni;
-    P.hist_blocks = (int32_t)((cap + kSortBlock - 1) / kSortBlock);
-    const int64_t hist_n = (int64_t)kRadix * P.hist_blocks;
+    P.item_blocks = (int32_t)((ni + kSortBlock - 1) / kSortBlock);
+    P.pair_blocks = (int32_t)((cap + kSortBlock - 1) / kSortBlock);
+    P.tile_bits = bits_of(P.total_tiles - 1);
+    P.view_bits = bits_of(f->n_views);
+    P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
+    const int64_t hist_n = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);
     const int64_t scan_words = (ni + kScanBlock - 1) / kScanBlock + 1;
     const int64_t part_words = 2 * ((ni + 255) / 256) + 2;
     size_t o = 0;
@@ -88,24 +94,25 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     memset(&L, 0, sizeof(L));
     L.status = 0;
     L.n_pairs = offsetof(WsHeader, n_pairs);
-    L.sort_sel = offsetof(WsHeader, sort_sel);
     L.depth_range = offsetof(WsHeader, depth_min);
     o = sizeof(WsHeader);
     L.records = o;            o = align_up(o + sizeof(Record) * (size_t)ni);
     L.counts = o;             o = align_up(o + 4 * (size_t)ni);
+    P.icounts = o;            o = align_up(o + 4 * (size_t)ni);
     L.offsets = o;            o = align_up(o + 4 * (size_t)ni);
     P.scan_tmp = o;           o = align_up(o + 4 * (size_t)(scan_words > part_words ? scan_words : part_words));
-    L.keys0 = o;              o = align_up(o + 8 * (size_t)cap);
-    L.keys1 = o;              o = align_up(o + 8 * (size_t)cap);
-    L.values0 = o;            o = align_up(o + 4 * (size_t)cap);
-    L.values1 = o;            o = align_up(o + 4 * (size_t)cap);
+    for (int b = 0; b < 2; ++b) { P.ikeys[b] = o; o = align_up(o + 8 * (size_t)ni); }
+    for (int b = 0; b < 2; ++b) { P.ivals[b] = o; o = align_up(o + 4 * (size_t)ni); }
+    for (int b = 0; b < 2; ++b) { P.ptile[b] = o; o = align_up(o + 4 * (size_t)cap); }
+    for (int b = 0; b < 2; ++b) { P.pval[b] = o; o = align_up(o + 4 * (size_t)cap); }
     P.hist = o;               o = align_up(o + 4 * (size_t)hist_n);
     P.hist_tmp = o;           o = align_up(o + 4 * (size_t)((hist_n + kScanBlock - 1) / kScanBlock + 1));
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
     L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
     P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
+    L.pair_tiles = P.ptile[P.pair_passes & 1];
+    L.pair_values = P.pval[P.pair_passes & 1];
     L.total = o;
-    P.depth_part = P.scan_tmp;
     if (need_ws && f->ws_bytes < L.total) return XG_EINVAL;
     return XG_OK;
 }
@@ -114,28 +121,34 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     char *b = (char *)f->ws;
     Ws w;
     w.hdr = (WsHeader *)b;
-    const int64_t ni = P.n_items;
     w.rec = (Record *)(b + P.lay.records);
     w.counts = (uint32_t *)(b + P.lay.counts);
+    w.icounts = (uint32_t *)(b + P.icounts);
     w.offsets = (uint32_t *)(b + P.lay.offsets);
     w.scan_tmp = (uint32_t *)(b + P.scan_tmp);
-    w.keys[0] = (uint64_t *)(b + P.lay.keys0);
-    w.keys[1] = (uint64_t *)(b + P.lay.keys1);
-    w.values[0] = (uint32_t *)(b + P.lay.values0);
-    w.values[1] = (uint32_t *)(b + P.lay.values1);
+    for (int k = 0; k < 2; ++k) {
+        w.ikeys[k] = (uint64_t *)(b + P.ikeys[k]);
+        w.ivals[k] = (uint32_t *)(b + P.ivals[k]);
+        w.ptile[k] = (uint32_t *)(b + P.ptile[k]);
+        w.pval[k] = (uint32_t *)(b + P.pval[k]);
+    }
     w.hist = (uint32_t *)(b + P.hist);
     w.hist_tmp = (uint32_t *)(b + P.hist_tmp);
     w.ranges = (uint32_t *)(b + P.lay.ranges);
     w.grad2d = (float *)(b + P.lay.grad2d);
     w.tile_order = (int32_t *)(b + P.tile_order);
     w.cap = f->pair_capacity;
-    w.n_items = ni;
+    w.n_items = P.n_items;
     w.total_tiles = P.total_tiles;
     w.total_pixels = P.total_px;
     w.n = f->n;
     w.n_views = f->n_views;
-    w.tile_bits = P.total_tiles <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(P.total_tiles - 1));
-    w.hist_blocks = P.hist_blocks;
+    w.tile_bits = P.tile_bits;
+    w.view_bits = P.view_bits;
+    w.item_blocks = P.item_blocks;
+    w.pair_blocks = P.pair_blocks;
+    w.pair_passes = P.pair_passes;
+    w.pair_sel = P.pair_passes & 1;
     return w;
 }
 
@@ -280,10 +293,13 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
     const Params p = params_of(f->settings);
     hipError_t e = hipSuccess;
     if (ws.n_items > 0) {
-        e = launch_scan(ws.counts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
-                        &ws.hdr->status, ws.cap, s);
+        e = launch_sort_items(ws, s);
+        if (e == hipSuccess) e = launch_gather_counts(ws, s);
+        if (e == hipSuccess)
+            e = launch_scan(ws.icounts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
+                            &ws.hdr->status, ws.cap, s);
         if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
-        if (e == hipSuccess) e = launch_sort(ws, s);
+        if (e == hipSuccess) e = launch_sort_pairs(ws, s);
     }
     if (e == hipSuccess) e = launch_ranges(ws, s);
     if (e == hipSuccess) e = launch_tile_order(ws, s);

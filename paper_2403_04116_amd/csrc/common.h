@@ -15,7 +15,7 @@ constexpr int kWave = 64;
 struct WsHeader {
     int32_t status;        // XG_OK / XG_ECAPACITY
     int32_t n_pairs;       // pairs requested by the scan (may exceed capacity)
-    int32_t sort_sel;      // which key/value buffer holds the sorted pairs
+    int32_t item_sel;      // which item key/value buffer holds the depth-sorted items
     uint32_t depth_min;    // min float32 depth bits over kept (view, Gaussian)
     uint32_t depth_max;    // max float32 depth bits
     int32_t queue_fwd;     // persistent forward tile queue head
@@ -61,11 +61,14 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 struct Ws {
     WsHeader *hdr;
     Record *rec;
-    uint32_t *counts;
-    uint32_t *offsets;
+    uint32_t *counts;      // tiles per (view, Gaussian), in (view, Gaussian) order
+    uint32_t *icounts;     // the same counts in depth-sorted item order
+    uint32_t *offsets;     // exclusive scan of icounts
     uint32_t *scan_tmp;
-    uint64_t *keys[2];
-    uint32_t *values[2];
+    uint64_t *ikeys[2];    // item sort keys (view << 32 | depth bits)
+    uint32_t *ivals[2];    // item sort values ((view, Gaussian) index)
+    uint32_t *ptile[2];    // pair sort keys (global tile id)
+    uint32_t *pval[2];     // pair sort values (Gaussian index)
     uint32_t *hist;
     uint32_t *hist_tmp;
     uint32_t *ranges;
@@ -78,7 +81,11 @@ struct Ws {
     int32_t n;
     int32_t n_views;
     int32_t tile_bits;     // bits of the largest global tile id
-    int32_t hist_blocks;   // radix-sort blocks for the capacity
+    int32_t view_bits;     // bits of n_views (culled items sort after view n_views - 1)
+    int32_t item_blocks;   // radix-sort blocks over the items
+    int32_t pair_blocks;   // radix-sort blocks over the pair capacity
+    int32_t pair_passes;   // 8-bit passes over the tile id
+    int32_t pair_sel;      // buffer holding the tile-sorted pairs (pair_passes & 1)
 };
 
 // Scalar constants of one rendering.
@@ -108,8 +115,10 @@ hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camer
                              const Params &p, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
                        int32_t *total, int32_t *status, int64_t cap, hipStream_t s);
+hipError_t launch_sort_items(const Ws &ws, hipStream_t s);
+hipError_t launch_gather_counts(const Ws &ws, hipStream_t s);
 hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s);
-hipError_t launch_sort(const Ws &ws, hipStream_t s);
+hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s);
 hipError_t launch_ranges(const Ws &ws, hipStream_t s);
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p,

@@ -153,7 +153,7 @@ __global__ void k_reset(WsHeader *h) {
     if (threadIdx.x == 0) {
         h->status = XG_OK;
         h->n_pairs = 0;
-        h->sort_sel = 0;
+        h->item_sel = 0;
         h->depth_min = 0xffffffffu;
         h->depth_max = 0u;
         h->queue_fwd = 0;
@@ -252,33 +252,34 @@ __global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_
     }
 }
 
-// Duplicate-with-key: one (key, value) per tile of the rectangle, at the
-// (view, Gaussian)'s scanned offset.  Pairs past the capacity are dropped
-// (the scan has raised XG_ECAPACITY).
+// Duplicate-with-key, in depth order: item j of the depth-sorted items
+// writes one (global tile id, Gaussian index) pair per tile of its
+// rectangle at its scanned offset.  A stable sort of these pairs by tile
+// then leaves every tile's list in (depth, index) order.  Pairs past the
+// capacity are dropped (the scan has raised XG_ECAPACITY).
 __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int tile) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ws.n_items) return;
-    const uint32_t cnt = ws.counts[idx];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ws.n_items) return;
+    const uint32_t cnt = ws.icounts[j];
     if (cnt == 0) return;
-    const uint32_t off = ws.offsets[idx];
+    const uint32_t off = ws.offsets[j];
     if ((int64_t)off + cnt > ws.cap) return;
-    const int v = (int)(idx / ws.n);
-    const uint32_t i = (uint32_t)(idx - (int64_t)v * ws.n);
+    const uint32_t idx = ws.ivals[ws.hdr->item_sel & 1][j];
+    const int v = (int)(idx / (uint32_t)ws.n);
+    const uint32_t i = idx - (uint32_t)v * (uint32_t)ws.n;
     const int4 rc = ws.rec[idx].c;
-    const uint32_t dbits = __float_as_uint(ws.rec[idx].b.w);
     const xg_camera &c = cams[v];
     const int txn = (c.width + tile - 1) / tile;
     const int tx0 = (rc.z & 0xffff) / tile, tx1 = (rc.z >> 16) / tile;
     const int ty0 = (rc.w & 0xffff) / tile, ty1 = (rc.w >> 16) / tile;
-    uint64_t *kk = ws.keys[0] + off;
-    uint32_t *vv = ws.values[0] + off;
-    int n = 0;
+    uint32_t *tt = ws.ptile[0] + off;
+    uint32_t *vv = ws.pval[0] + off;
+    int m = 0;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
-            const uint64_t gt = (uint64_t)(c.tile_offset + ty * txn + tx);
-            kk[n] = (gt << 32) | dbits;
-            vv[n] = i;
-            ++n;
+            tt[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
+            vv[m] = i;
+            ++m;
         }
 }
 
@@ -439,6 +440,7 @@ hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camer
 }
 
 hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s) {
+    // one thread per depth-sorted item
     const int64_t nb = (ws.n_items + 255) / 256;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws, cams, p.tile);
     return hipGetLastError();

@@ -160,7 +160,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
 
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
     const uint32_t e = ws.ranges[2 * (int64_t)tile + 1];
-    const uint32_t *vals = ws.values[ws.hdr->sort_sel & 1];
+    const uint32_t *vals = ws.pval[ws.pair_sel];
     const float amin = p.alpha_min, amax = p.alpha_max, tmin = p.t_min;
     uint16_t *list = sh.list[NW > 1 ? w : 0];
 
@@ -326,7 +326,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     const float pyr = (float)(py - tg.ry) + 0.5f;
 
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
-    const uint32_t *vals = ws.values[ws.hdr->sort_sel & 1];
+    const uint32_t *vals = ws.pval[ws.pair_sel];
     const float amin = p.alpha_min, amax = p.alpha_max;
     uint16_t *list = sh.list[NW > 1 ? w : 0];
 

@@ -100,14 +100,20 @@ class Frame:
         return int(self.ws_tensor(self.layout.n_pairs, torch.int32, 1).item())
 
     def sorted_pairs(self):
-        """(keys, values, ranges) views of the sorted lists (synchronises)."""
+        """(keys, values, ranges) of the sorted lists, for inspection
+        (synchronises).  keys[p] = tile << 32 | depth bits, rebuilt from the
+        stored tile ids and the render records' depth words."""
         p = self.n_pairs()
-        sel = int(self.ws_tensor(self.layout.sort_sel, torch.int32, 1).item())
-        ko = self.layout.keys1 if sel else self.layout.keys0
-        vo = self.layout.values1 if sel else self.layout.values0
-        keys = self.ws_tensor(ko, torch.int64, p)
-        vals = self.ws_tensor(vo, torch.int32, p)
+        if self.status() != X.XG_OK:
+            p = 0
+        tiles = self.ws_tensor(self.layout.pair_tiles, torch.int32, p).long()
+        vals = self.ws_tensor(self.layout.pair_values, torch.int32, p)
         ranges = self.ws_tensor(self.layout.ranges, torch.int32, 2 * self.total_tiles)
+        toff = torch.tensor([c.tile_offset for c in self.cams], dtype=torch.int64, device=self.device)
+        view = torch.searchsorted(toff, tiles, right=True) - 1
+        rec = self.ws_tensor(self.layout.records, torch.int32, 16 * self.n * self.n_views)
+        depth = rec.view(-1, 16)[view * self.n + vals.long(), 7].long() & 0xFFFFFFFF
+        keys = (tiles << 32) | depth
         return keys, vals, ranges.view(self.total_tiles, 2)
 
     # -- stages --------------------------------------------------------------

@@ -86,11 +86,11 @@ def test_workspace_size_grows_with_capacity_and_views():
     f2, _ = _frame(cap=100000)
     f3, _ = _frame(cap=1000, views=((64, 64), (64, 64)))
     s1, s2, s3 = (P.xg_workspace_size(f) for f in (f1, f2, f3))
-    assert s2 > s1 + 12 * (100000 - 1000) * 2 - 1
+    assert s2 > s1 + 8 * (100000 - 1000) * 2 - 1
     assert s3 > s1
     lay = P.xg_ws_layout_of(f1)
     assert lay.total == s1
-    offs = [lay.records, lay.counts, lay.offsets, lay.keys0, lay.keys1, lay.values0, lay.values1,
+    offs = [lay.records, lay.counts, lay.offsets, min(lay.pair_tiles, lay.pair_values),
             lay.ranges, lay.grad2d]
     assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
 
