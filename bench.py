@@ -43,7 +43,20 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="after timing, run 3 plain device copies of MB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    """Hash of the blend kernels' source; a stored HBM-traffic figure is only
+    reported while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("render.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2403_04116_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -149,7 +162,9 @@ def main():
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
-            if tj.get("kernel") == dom and tj.get("workload") == args.workload:
+            if (tj.get("kernel") == dom and tj.get("workload") == args.workload
+                    and tj.get("source_hash") == kernel_source_hash()
+                    and tj.get("tile") == args.tile and tj.get("lds_batch") == args.lds):
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
@@ -182,6 +197,16 @@ def main():
         per_view = {"value": w.n_views / (ms_pv * 1e-3), "ms_per_step": ms_pv}
 
     value = w.n_views / (ms_batched * 1e-3)
+
+    if args.calibrate_copy > 0:
+        # a plain copy of known size, for scaling the HBM byte counters
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of views ---------
     cpu = None
@@ -234,6 +259,7 @@ def main():
                  "revisited": upto},
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),
         "wall_s": wall_b,
+        "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(res))
 
