@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="also time the batched step captured as one HIP graph (1/0)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run 3 plain device copies of MB MiB (counter calibration)")
     return ap.parse_args()
@@ -169,6 +171,27 @@ def main():
         except (OSError, ValueError):
             traffic = None
 
+    # ---- the same batched step captured as one HIP graph --------------------
+    graph = None
+    if args.graph:
+        from paper_2403_04116_amd.step import TrainStep
+        ts = TrainStep(frame, g, target, scale, grads=grads)
+        ts.capture()
+        for _ in range(args.warmup):
+            ts.replay()
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(args.steps):
+            ts.replay()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        assert ts.check(), "pair capacity exceeded during graph replay"
+        ms_graph = g0.elapsed_time(g1) / args.steps
+        graph = {"value": w.n_views / (ms_graph * 1e-3), "ms_per_step": ms_graph}
+        del ts
+
     # ---- per-view path ------------------------------------------------------
     per_view = None
     if not args.no_per_view:
@@ -252,6 +275,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "launch_ms": dom_ms, "flops_per_launch": dom_flops},
         "cpu_baseline": cpu,
+        "graph": graph,
         "per_view": per_view,
         "batched_over_per_view": (value / per_view["value"]) if per_view else None,
         "kernels_ms": {"k_render_fwd": fwd_ms, "k_render_bwd": bwd_ms},
