@@ -225,6 +225,55 @@ xg_status xg_preprocess_bwd(const xg_frame *f /* [host] */, const xg_gaussians *
  * [3][total pixels]. */
 xg_status xg_render_counts(const xg_frame *f /* [host] */, int32_t *counts, void *stream);
 
+/* Raw (unconstrained) trainable parameters, float32 SoA, contiguous:
+ * means[n][3], log_scales[n][3] (scales = exp), quats[n][4] (the renderer
+ * normalises), opacity_logit[n] (opacity = sigmoid), feature[n]
+ * (radiation intensity = sigmoid(feature_weight * feature), Eq. 3 with one
+ * feature). */
+typedef struct {
+    float *means, *log_scales, *quats, *opacity_logit, *feature;
+    int32_t n;
+} xg_params;
+
+/* Adam settings.  The paper's (Sec. 4.1): beta1 0.9, beta2 0.999, eps
+ * 1e-15; learning rates: positions 1.9e-4 decaying exponentially to 1.9e-6
+ * over 2e4 steps, feature 2e-3, opacity 8e-3, scaling 5e-3, rotation 1e-3.
+ * The position rate at step t (1-based) is
+ * exp((1 - f) ln(lr_means_start) + f ln(lr_means_end)),
+ * f = min(t - 1, lr_means_steps) / lr_means_steps.  The betas are double:
+ * 0.999 rounded to float moves 1 - beta2 by 1.3e-5 relative, so the
+ * library forms 1 - beta, beta^t and the rate schedule in double and rounds
+ * the results once to float. */
+typedef struct {
+    float lr_means_start, lr_means_end;
+    int32_t lr_means_steps;
+    float lr_scales, lr_quats, lr_opacity, lr_feature;
+    float eps;
+    float feature_weight;
+    int32_t reserved;       /* 0 */
+    double beta1, beta2;
+} xg_adam;
+
+/* Fused optimiser step (gradients from xg_preprocess_bwd are with respect
+ * to the activated parameters).  With t = *step + 1 read from device
+ * memory: per raw scalar, chain rule through the activation at the current
+ * value, m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); then writes the
+ * activated copies scales[n][3], opacity[n], intensity[n] (means and quats
+ * are used raw) and advances *step.  m and v are float[12 n] in the order
+ * means, log_scales, quats, opacity_logit, feature; *step starts at 0.
+ * The step count lives on the device so a captured step replays correctly.
+ * gate (device, nullable): when it reads nonzero at execution time the
+ * step is skipped (nothing written, *step unchanged); pass the frame's
+ * status word (xg_ws_layout.status) so a step whose pairs overflowed the
+ * capacity never reaches the parameters.  All array pointers device;
+ * updates in place.  EINVAL: null pointers, beta outside [0, 1), eps < 0,
+ * non-finite or negative rates, lr_means_steps < 1, reserved != 0. */
+xg_status xg_adam_step(const xg_params *p /* [host] struct of device ptrs */,
+                       const xg_grads *g /* [host] struct of device ptrs */, float *m, float *v,
+                       int32_t *step, const xg_adam *c /* [host] */, float *scales, float *opacity,
+                       float *intensity, const int32_t *gate, void *stream);
+
 /* L1 term of Eq. 11: dl_dimage[p] = scale * sign(image[p] - target[p])
  * (0 where equal), for n_pixels pixels. */
 xg_status xg_l1_grad(const float *image, const float *target, float *dl_dimage,

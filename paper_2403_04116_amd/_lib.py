@@ -57,6 +57,19 @@ class XgGrads(C.Structure):
                 ("opacity", C.c_void_p), ("intensity", C.c_void_p)]
 
 
+class XgParams(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("feature", C.c_void_p), ("n", C.c_int32)]
+
+
+class XgAdam(C.Structure):
+    _fields_ = [("lr_means_start", C.c_float), ("lr_means_end", C.c_float),
+                ("lr_means_steps", C.c_int32), ("lr_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_feature", C.c_float), ("eps", C.c_float),
+                ("feature_weight", C.c_float), ("reserved", C.c_int32), ("beta1", C.c_double),
+                ("beta2", C.c_double)]
+
+
 class XgFrame(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_views", C.c_int32), ("cams", C.POINTER(XgCamera)),
                 ("cams_dev", C.c_void_p), ("settings", XgSettings), ("ws", C.c_void_p),
@@ -104,6 +117,9 @@ _L.xg_preprocess_bwd.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), C.P
 _L.xg_render_counts.restype = _S
 _L.xg_render_counts.argtypes = [C.POINTER(XgFrame), _P, _P]
 _L.xg_last_error.restype = C.c_char_p
+_L.xg_adam_step.restype = _S
+_L.xg_adam_step.argtypes = [C.POINTER(XgParams), C.POINTER(XgGrads), _P, _P, _P, C.POINTER(XgAdam),
+                            _P, _P, _P, _P, _P]
 _L.xg_l1_grad.restype = _S
 _L.xg_l1_grad.argtypes = [_P, _P, _P, C.c_int64, C.c_float, _P]
 
@@ -113,7 +129,7 @@ if _L.xg_abi_version() != ABI_VERSION:
 EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_camera_from_scanner",
             "xg_layout_views", "xg_ws_layout_of", "xg_workspace_size", "xg_preprocess",
             "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
-            "xg_render_counts", "xg_l1_grad", "xg_last_error")
+            "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step")
 
 
 def lib() -> C.CDLL:
@@ -195,3 +211,9 @@ def xg_render_counts(frame: XgFrame, counts: int, stream: int = 0) -> None:
 def xg_l1_grad(image: int, target: int, dl_dimage: int, n_pixels: int, scale: float,
                stream: int = 0) -> None:
     _check(_L.xg_l1_grad(image, target, dl_dimage, n_pixels, scale, stream), "xg_l1_grad")
+
+
+def xg_adam_step(params: XgParams, grads: XgGrads, m: int, v: int, step: int, cfg: XgAdam,
+                 scales: int, opacity: int, intensity: int, gate: int = 0, stream: int = 0) -> None:
+    _check(_L.xg_adam_step(C.byref(params), C.byref(grads), m, v, step, C.byref(cfg), scales,
+                           opacity, intensity, gate or None, stream), "xg_adam_step")

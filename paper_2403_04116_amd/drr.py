@@ -96,6 +96,10 @@ class Frame:
     def status(self) -> int:
         return int(self.ws_tensor(self.layout.status, torch.int32, 1).item())
 
+    def status_ptr(self) -> int:
+        """Device address of the status word (valid until the next reallocation)."""
+        return self.ws.data_ptr() + self.layout.status
+
     def n_pairs(self) -> int:
         return int(self.ws_tensor(self.layout.n_pairs, torch.int32, 1).item())
 

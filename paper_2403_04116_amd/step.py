@@ -21,7 +21,7 @@ from .drr import PARAMS, Frame, gaussians_struct
 
 class TrainStep:
     def __init__(self, frame: Frame, g: dict, target: torch.Tensor, scale: float,
-                 grads: dict | None = None, zero_grads: bool = True):
+                 grads: dict | None = None, zero_grads: bool = True, optimizer=None):
         self.frame = frame
         self.g = g
         self.target = target
@@ -31,10 +31,14 @@ class TrainStep:
         self.dl = torch.empty_like(self.image)
         self.grads = frame.new_grads(g) if grads is None else grads
         self.graph = None
-        self.post = []   # extra enqueue callables run after the backward (e.g. an optimiser)
+        self.post = []   # extra enqueue callables run after the backward
+        # FusedAdam over the Gaussians in ``g`` (its activated copies are ``g``);
+        # gated by the frame's status word, so an overflowed step changes nothing
+        self.optimizer = optimizer
 
-    def run(self, stream=None) -> None:
-        """Enqueues one step on ``stream`` (default: the current stream)."""
+    def run(self, stream=None, optimize: bool = True) -> None:
+        """Enqueues one step on ``stream`` (default: the current stream);
+        ``optimize=False`` leaves the optimiser out."""
         s = int((stream or torch.cuda.current_stream()).cuda_stream)
         f = self.frame
         gs = gaussians_struct(self.g)
@@ -51,15 +55,18 @@ class TrainStep:
         X.xg_render_bwd(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
                         self.n_contrib.data_ptr(), s)
         X.xg_preprocess_bwd(f.frame, gs, gr, s)
+        if optimize and self.optimizer is not None:
+            self.optimizer.step(self.grads, s, gate=f.status_ptr())
         for fn in self.post:
             fn(s)
 
     def capture(self) -> None:
-        """Captures run() into a graph (after one eager warm-up on a side stream)."""
+        """Captures run() into a graph (after one eager warm-up on a side
+        stream, which leaves the optimiser out so the parameters do not move)."""
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            self.run()
+            self.run(optimize=False)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()

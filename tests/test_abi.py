@@ -45,6 +45,30 @@ def test_struct_sizes_match_header():
     assert C.sizeof(X.XgCamera) == 80
     assert C.sizeof(X.XgSettings) == 32
     assert C.sizeof(X.XgFrame) == 80
+    assert C.sizeof(X.XgAdam) == 56
+    assert X.XgAdam.beta1.offset == 40
+    assert C.sizeof(X.XgParams) == 48
+    assert C.sizeof(X.XgGrads) == 40
+
+
+def _adam_cfg(**kw):
+    c = dict(lr_means_start=1.9e-4, lr_means_end=1.9e-6, lr_means_steps=20000, lr_scales=5e-3,
+             lr_quats=1e-3, lr_opacity=8e-3, lr_feature=2e-3, eps=1e-15, feature_weight=1.0,
+             reserved=0, beta1=0.9, beta2=0.999)
+    c.update(kw)
+    return X.XgAdam(**c)
+
+
+@pytest.mark.parametrize("bad", [dict(beta2=1.0), dict(beta1=-0.1), dict(eps=-1.0),
+                                 dict(lr_means_steps=0), dict(lr_means_end=0.0),
+                                 dict(lr_quats=float("nan")), dict(reserved=1)])
+def test_invalid_adam_settings_rejected_before_any_hip_call(bad):
+    fake = 4096          # never dereferenced: validation fails first
+    p = X.XgParams(fake, fake, fake, fake, fake, 10)
+    g = X.XgGrads(fake, fake, fake, fake, fake)
+    with pytest.raises(X.XgError) as e:
+        X.xg_adam_step(p, g, fake, fake, fake, _adam_cfg(**bad), fake, fake, fake, 0, 0)
+    assert e.value.status == X.XG_EINVAL
 
 
 @pytest.mark.parametrize("phi", [0.0, 0.7, math.pi / 2, math.pi, 5.5, 2 * math.pi])
