@@ -210,6 +210,27 @@ xg_status xg_render_fwd(const xg_frame *f /* [host] */, const xg_gaussians *g /*
 xg_status xg_render_bwd(const xg_frame *f /* [host] */, const float *dl_dimage,
                         const float *final_t, const int32_t *n_contrib, void *stream);
 
+/* Stored-transmittance variant of stages 3 and 4.  The forward
+ * additionally keeps, for every pixel, the transmittance in front of each
+ * of its first `slots` contributors (the T_j of Eq. 10 that the adjoint
+ * needs); the backward reads them instead of dividing the transmittance
+ * back, and divides only for contributors beyond `slots`.  Results equal
+ * xg_render_fwd / xg_render_bwd up to the rounding of that division.
+ * store: device buffer of at least xg_store_size(f, slots) bytes,
+ * 256-byte aligned, caller-owned, written by the forward and read by the
+ * backward of the same frame and tile size (its layout is per tile:
+ * int32 contributor counts, then float transmittances slot-major).
+ * EINVAL: slots outside [1, XG_MAX_STORE_SLOTS], a short or misaligned
+ * store, or XG_F_PERSISTENT set. */
+#define XG_MAX_STORE_SLOTS 4096
+xg_status xg_store_size(const xg_frame *f /* [host] */, int32_t slots, int64_t *bytes /* [host] */);
+xg_status xg_render_fwd_store(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                              float *image, float *final_t, int32_t *n_contrib, void *store,
+                              int32_t slots, int64_t store_bytes, void *stream);
+xg_status xg_render_bwd_store(const xg_frame *f /* [host] */, const float *dl_dimage,
+                              const float *final_t, const int32_t *n_contrib, const void *store,
+                              int32_t slots, int64_t store_bytes, void *stream);
+
 /* Stage 5 (adjoint of Eq. 7-9): maps the 2-D gradients of every view to
  * means, scales, quaternions (through their normalisation), opacity and
  * intensity, summing over views in registers (one thread per Gaussian, no

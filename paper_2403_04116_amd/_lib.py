@@ -120,6 +120,13 @@ _L.xg_last_error.restype = C.c_char_p
 _L.xg_adam_step.restype = _S
 _L.xg_adam_step.argtypes = [C.POINTER(XgParams), C.POINTER(XgGrads), _P, _P, _P, C.POINTER(XgAdam),
                             _P, _P, _P, _P, _P]
+_L.xg_store_size.restype = _S
+_L.xg_store_size.argtypes = [C.POINTER(XgFrame), C.c_int32, C.POINTER(C.c_int64)]
+_L.xg_render_fwd_store.restype = _S
+_L.xg_render_fwd_store.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P,
+                                   C.c_int32, C.c_int64, _P]
+_L.xg_render_bwd_store.restype = _S
+_L.xg_render_bwd_store.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P, C.c_int32, C.c_int64, _P]
 _L.xg_l1_grad.restype = _S
 _L.xg_l1_grad.argtypes = [_P, _P, _P, C.c_int64, C.c_float, _P]
 
@@ -129,7 +136,9 @@ if _L.xg_abi_version() != ABI_VERSION:
 EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_camera_from_scanner",
             "xg_layout_views", "xg_ws_layout_of", "xg_workspace_size", "xg_preprocess",
             "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
-            "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step")
+            "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
+            "xg_render_fwd_store", "xg_render_bwd_store")
+MAX_STORE_SLOTS = 4096
 
 
 def lib() -> C.CDLL:
@@ -191,6 +200,24 @@ def xg_render_fwd(frame: XgFrame, g: XgGaussians, image: int, final_t: int, n_co
                   stream: int = 0) -> None:
     _check(_L.xg_render_fwd(C.byref(frame), C.byref(g), image, final_t, n_contrib, stream),
            "xg_render_fwd")
+
+
+def xg_store_size(frame: XgFrame, slots: int) -> int:
+    b = C.c_int64()
+    _check(_L.xg_store_size(C.byref(frame), slots, C.byref(b)), "xg_store_size")
+    return b.value
+
+
+def xg_render_fwd_store(frame: XgFrame, g: XgGaussians, image: int, final_t: int, n_contrib: int,
+                        store: int, slots: int, store_bytes: int, stream: int = 0) -> None:
+    _check(_L.xg_render_fwd_store(C.byref(frame), C.byref(g), image, final_t, n_contrib, store,
+                                  slots, store_bytes, stream), "xg_render_fwd_store")
+
+
+def xg_render_bwd_store(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int, store: int,
+                        slots: int, store_bytes: int, stream: int = 0) -> None:
+    _check(_L.xg_render_bwd_store(C.byref(frame), dl_dimage, final_t, n_contrib, store, slots,
+                                  store_bytes, stream), "xg_render_bwd_store")
 
 
 def xg_render_bwd(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int,

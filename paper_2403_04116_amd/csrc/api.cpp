@@ -316,7 +316,7 @@ xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, 
     const Params p = params_of(f->settings);
     return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib,
                                         (f->settings.flags & XG_F_PERSISTENT) != 0,
-                                        (hipStream_t)stream));
+                                        TStore{nullptr, nullptr, 0}, (hipStream_t)stream));
 }
 
 xg_status xg_render_bwd(const xg_frame *f, const float *dl_dimage, const float *final_t,
@@ -329,6 +329,72 @@ xg_status xg_render_bwd(const xg_frame *f, const float *dl_dimage, const float *
     const Params p = params_of(f->settings);
     return hip_status(launch_render_bwd(ws, f->cams_dev, p, dl_dimage, final_t, n_contrib,
                                         (f->settings.flags & XG_F_PERSISTENT) != 0,
+                                        TStore{nullptr, nullptr, 0}, (hipStream_t)stream));
+}
+
+// Stored-transmittance buffer: int32 count[tiles][tile^2], then float
+// t[tiles][slots][tile^2], each part rounded up to 256 bytes.
+static int64_t store_count_bytes(const Plan &P, const xg_settings &s) {
+    const int64_t px = (int64_t)P.total_tiles * s.tile * s.tile;
+    return (px * 4 + 255) / 256 * 256;
+}
+
+static int64_t store_bytes_of(const Plan &P, const xg_settings &s, int32_t slots) {
+    const int64_t px = (int64_t)P.total_tiles * s.tile * s.tile;
+    return store_count_bytes(P, s) + (px * slots * 4 + 255) / 256 * 256;
+}
+
+static xg_status store_of(const xg_frame *f, const Plan &P, const void *store, int32_t slots,
+                          int64_t store_bytes, TStore &ts) {
+    if (slots < 1 || slots > XG_MAX_STORE_SLOTS) return XG_EINVAL;
+    if (!store || ((uintptr_t)store & 255) != 0) return XG_EINVAL;
+    if (f->settings.flags & XG_F_PERSISTENT) return XG_EINVAL;
+    if (store_bytes < store_bytes_of(P, f->settings, slots)) return XG_EINVAL;
+    char *base = (char *)const_cast<void *>(store);
+    ts.count = (int32_t *)base;
+    ts.t = (float *)(base + store_count_bytes(P, f->settings));
+    ts.slots = slots;
+    return XG_OK;
+}
+
+xg_status xg_store_size(const xg_frame *f, int32_t slots, int64_t *bytes) {
+    if (!bytes || slots < 1 || slots > XG_MAX_STORE_SLOTS) return XG_EINVAL;
+    Plan P;
+    xg_status st = make_plan(f, false, P);
+    if (st != XG_OK) return st;
+    *bytes = store_bytes_of(P, f->settings, slots);
+    return XG_OK;
+}
+
+xg_status xg_render_fwd_store(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
+                              int32_t *n_contrib, void *store, int32_t slots, int64_t store_bytes,
+                              void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !image || !final_t || !n_contrib) return XG_EINVAL;
+    TStore ts;
+    st = store_of(f, P, store, slots, store_bytes, ts);
+    if (st != XG_OK) return st;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib, 0, ts,
+                                        (hipStream_t)stream));
+}
+
+xg_status xg_render_bwd_store(const xg_frame *f, const float *dl_dimage, const float *final_t,
+                              const int32_t *n_contrib, const void *store, int32_t slots,
+                              int64_t store_bytes, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!dl_dimage || !final_t || !n_contrib) return XG_EINVAL;
+    TStore ts;
+    st = store_of(f, P, store, slots, store_bytes, ts);
+    if (st != XG_OK) return st;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_render_bwd(ws, f->cams_dev, p, dl_dimage, final_t, n_contrib, 0, ts,
                                         (hipStream_t)stream));
 }
 

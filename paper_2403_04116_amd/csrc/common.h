@@ -121,12 +121,22 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s);
 hipError_t launch_ranges(const Ws &ws, hipStream_t s);
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
+// Per-pixel stored transmittances of the stored-list variant: count[tile][px]
+// contributors, then t[tile][slot][px] = T before contributor `slot` (the
+// first `slots` contributors of each pixel; px = thread index in the tile).
+struct TStore {
+    float *t;
+    int32_t *count;
+    int slots;
+};
+
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              float *image, float *final_t, int32_t *n_contrib,
-                             int persistent, hipStream_t s);
+                             int persistent, const TStore &ts, hipStream_t s);
 hipError_t launch_render_bwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              const float *dl_dimage, const float *final_t,
-                             const int32_t *n_contrib, int persistent, hipStream_t s);
+                             const int32_t *n_contrib, int persistent, const TStore &ts,
+                             hipStream_t s);
 hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Params &p,
                                 int32_t *counts, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,

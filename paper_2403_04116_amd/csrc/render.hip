@@ -137,10 +137,11 @@ struct BlendLds {
     int next;
 };
 
-template <int T, int B, bool COUNT>
+template <int T, int B, bool COUNT, bool STORE>
 __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera *cams,
                                          const Params &p, float *image, float *final_t,
-                                         int32_t *n_contrib, int32_t *counts, BlendLds<T, B> &sh) {
+                                         int32_t *n_contrib, int32_t *counts, const TStore &ts,
+                                         BlendLds<T, B> &sh) {
     constexpr int NT = T * T;
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
@@ -168,6 +169,8 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     int last = 0;
     int n_eval = 0, n_con = 0, n_upto = 0;
     bool done = !inside;
+    int nc = 0;   // contributors so far (stored variant)
+    float *tbase = STORE ? ts.t + (int64_t)tile * ts.slots * NT + threadIdx.x : nullptr;
     for (uint32_t b0 = s; b0 < e; b0 += B) {
         const int cnt = (int)min((uint32_t)B, e - b0);
         if (!__syncthreads_or(!done)) break;
@@ -189,6 +192,10 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             const bool term = con && Tn < tmin;
             const bool keep = con && !term;
             done = done || term;
+            if (STORE) {
+                if (keep && nc < ts.slots) tbase[(int64_t)nc * NT] = Tr;
+                nc += keep ? 1 : 0;
+            }
             C = keep ? fmaf(sb.z * ev.alpha, Tr, C) : C;
             Tr = keep ? Tn : Tr;
             last = keep ? (int)(b0 - s) + k + 1 : last;
@@ -201,6 +208,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             if ((j & 7) == 7 && !__any(!done)) break;
         }
     }
+    if (STORE) ts.count[(int64_t)tile * NT + threadIdx.x] = nc;
     if (inside) {
         const int64_t o = (int64_t)tg.pix_off + (int64_t)py * tg.W + px;
         if (COUNT) {
@@ -245,19 +253,23 @@ __device__ __forceinline__ void finish_queue(int32_t *queue, int32_t *done) {
 // counts[3][total pixels]; the blending decisions are the same.
 // PERSIST = true: a grid sized to the device's resident capacity takes
 // tiles from the work queue; otherwise one workgroup per tile.
-template <int T, int B, bool COUNT, bool PERSIST>
+// STORE = true: also keep the transmittance before each of the first
+// ts.slots contributors of every pixel (one workgroup per tile only).
+template <int T, int B, bool COUNT, bool PERSIST, bool STORE>
 __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *cams, Params p,
                                                       float *image, float *final_t,
-                                                      int32_t *n_contrib, int32_t *counts) {
+                                                      int32_t *n_contrib, int32_t *counts,
+                                                      TStore ts) {
     __shared__ BlendLds<T, B> sh;
     if (!PERSIST) {
-        fwd_tile<T, B, COUNT>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image, final_t, n_contrib, counts, sh);
+        fwd_tile<T, B, COUNT, STORE>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
+                                     final_t, n_contrib, counts, ts, sh);
         return;
     }
     for (;;) {
         const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_fwd, sh);
         if (tile < 0) break;
-        fwd_tile<T, B, COUNT>(tile, ws, cams, p, image, final_t, n_contrib, counts, sh);
+        fwd_tile<T, B, COUNT, false>(tile, ws, cams, p, image, final_t, n_contrib, counts, ts, sh);
     }
     finish_queue(&ws.hdr->queue_fwd, &ws.hdr->done_fwd);
 }
@@ -301,11 +313,11 @@ __device__ __forceinline__ float wave_reduce8(float v[8]) {
     return x;
 }
 
-template <int T, int B>
+template <int T, int B, bool STORE>
 __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera *cams,
                                          const Params &p, const float *dl_dimage,
                                          const float *final_t, const int32_t *n_contrib,
-                                         BlendLds<T, B> &sh) {
+                                         const TStore &ts, BlendLds<T, B> &sh) {
     constexpr int NT = T * T;
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
@@ -338,6 +350,16 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         Tr = final_t[o];
         last = n_contrib[o];
         if (g == 0.0f) last = 0;
+    }
+    // stored variant: index of the next contributor (counting down) and its
+    // stored transmittance, loaded one contributor ahead of its use;
+    // contributors past the stored slots divide the transmittance back
+    int c = -1;
+    float tnext = 0.0f;
+    const float *tbase = STORE ? ts.t + (int64_t)tile * ts.slots * NT + threadIdx.x : nullptr;
+    if (STORE) {
+        c = ts.count[(int64_t)tile * NT + threadIdx.x] - 1;
+        if (c >= 0 && c < ts.slots) tnext = tbase[(int64_t)c * NT];
     }
     int wmax = last;
     for (int off = kWave / 2; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, kWave));
@@ -374,7 +396,15 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             // contributor gets a zero upstream gradient (exact zeros in the
             // reduction) and keeps its transmittance and R.
             const float om = 1.0f - ev.alpha;
-            const float Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;   // T before this Gaussian
+            float Tj;   // T before this Gaussian
+            if (STORE) {
+                Tj = act ? (c < ts.slots ? tnext : Tr * __builtin_amdgcn_rcpf(om)) : Tr;
+                const int cn = act ? c - 1 : c;
+                if (act && cn >= 0 && cn < ts.slots) tnext = tbase[(int64_t)cn * NT];
+                c = cn;
+            } else {
+                Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;
+            }
             const float ge = act ? g : 0.0f;
             const float it = sb.z;
             const float gT = ge * Tj;
@@ -401,19 +431,20 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     }
 }
 
-template <int T, int B, bool PERSIST>
+template <int T, int B, bool PERSIST, bool STORE>
 __global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *cams, Params p,
                                                       const float *dl_dimage, const float *final_t,
-                                                      const int32_t *n_contrib) {
+                                                      const int32_t *n_contrib, TStore ts) {
     __shared__ BlendLds<T, B> sh;
     if (!PERSIST) {
-        bwd_tile<T, B>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, dl_dimage, final_t, n_contrib, sh);
+        bwd_tile<T, B, STORE>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, dl_dimage,
+                              final_t, n_contrib, ts, sh);
         return;
     }
     for (;;) {
         const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_bwd, sh);
         if (tile < 0) break;
-        bwd_tile<T, B>(tile, ws, cams, p, dl_dimage, final_t, n_contrib, sh);
+        bwd_tile<T, B, false>(tile, ws, cams, p, dl_dimage, final_t, n_contrib, ts, sh);
         __syncthreads();
     }
     finish_queue(&ws.hdr->queue_bwd, &ws.hdr->done_bwd);
@@ -433,16 +464,20 @@ unsigned resident_grid(K kernel, int threads, int64_t work) {
 
 template <int T, int B>
 hipError_t fwd_t(const Ws &ws, const xg_camera *cams, const Params &p, float *image, float *final_t,
-                 int32_t *n_contrib, int persistent, hipStream_t st) {
-    if (persistent) {
-        const unsigned g = resident_grid(k_render_fwd<T, B, false, true>, T * T, ws.total_tiles);
+                 int32_t *n_contrib, int persistent, const TStore &ts, hipStream_t st) {
+    const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
+    if (ts.t) {
+        if (persistent) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_render_fwd<T, B, false, false, true>), dim3(nb), dim3(T * T), 0, st, ws,
+                           cams, p, image, final_t, n_contrib, nullptr, ts);
+    } else if (persistent) {
+        const unsigned g = resident_grid(k_render_fwd<T, B, false, true, false>, T * T, ws.total_tiles);
         if (g == 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_render_fwd<T, B, false, true>), dim3(g), dim3(T * T), 0, st, ws, cams, p,
-                           image, final_t, n_contrib, nullptr);
+        hipLaunchKernelGGL((k_render_fwd<T, B, false, true, false>), dim3(g), dim3(T * T), 0, st, ws,
+                           cams, p, image, final_t, n_contrib, nullptr, ts);
     } else {
-        const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
-        hipLaunchKernelGGL((k_render_fwd<T, B, false, false>), dim3(nb), dim3(T * T), 0, st, ws, cams,
-                           p, image, final_t, n_contrib, nullptr);
+        hipLaunchKernelGGL((k_render_fwd<T, B, false, false, false>), dim3(nb), dim3(T * T), 0, st, ws,
+                           cams, p, image, final_t, n_contrib, nullptr, ts);
     }
     return hipGetLastError();
 }
@@ -451,23 +486,28 @@ template <int T, int B>
 hipError_t counts_t(const Ws &ws, const xg_camera *cams, const Params &p, int32_t *counts,
                     hipStream_t st) {
     const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
-    hipLaunchKernelGGL((k_render_fwd<T, B, true, false>), dim3(nb), dim3(T * T), 0, st, ws, cams, p,
-                       nullptr, nullptr, nullptr, counts);
+    hipLaunchKernelGGL((k_render_fwd<T, B, true, false, false>), dim3(nb), dim3(T * T), 0, st, ws,
+                       cams, p, nullptr, nullptr, nullptr, counts, TStore{nullptr, nullptr, 0});
     return hipGetLastError();
 }
 
 template <int T, int B>
 hipError_t bwd_t(const Ws &ws, const xg_camera *cams, const Params &p, const float *dl,
-                 const float *final_t, const int32_t *n_contrib, int persistent, hipStream_t st) {
-    if (persistent) {
-        const unsigned g = resident_grid(k_render_bwd<T, B, true>, T * T, ws.total_tiles);
+                 const float *final_t, const int32_t *n_contrib, int persistent, const TStore &ts,
+                 hipStream_t st) {
+    const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
+    if (ts.t) {
+        if (persistent) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_render_bwd<T, B, false, true>), dim3(nb), dim3(T * T), 0, st, ws, cams,
+                           p, dl, final_t, n_contrib, ts);
+    } else if (persistent) {
+        const unsigned g = resident_grid(k_render_bwd<T, B, true, false>, T * T, ws.total_tiles);
         if (g == 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_render_bwd<T, B, true>), dim3(g), dim3(T * T), 0, st, ws, cams, p, dl,
-                           final_t, n_contrib);
+        hipLaunchKernelGGL((k_render_bwd<T, B, true, false>), dim3(g), dim3(T * T), 0, st, ws, cams, p,
+                           dl, final_t, n_contrib, ts);
     } else {
-        const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
-        hipLaunchKernelGGL((k_render_bwd<T, B, false>), dim3(nb), dim3(T * T), 0, st, ws, cams, p, dl,
-                           final_t, n_contrib);
+        hipLaunchKernelGGL((k_render_bwd<T, B, false, false>), dim3(nb), dim3(T * T), 0, st, ws, cams,
+                           p, dl, final_t, n_contrib, ts);
     }
     return hipGetLastError();
 }
@@ -489,14 +529,16 @@ hipError_t bwd_t(const Ws &ws, const xg_camera *cams, const Params &p, const flo
     }
 
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p, float *image,
-                             float *final_t, int32_t *n_contrib, int persistent, hipStream_t s) {
-    XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, persistent, s)
+                             float *final_t, int32_t *n_contrib, int persistent, const TStore &ts,
+                             hipStream_t s) {
+    XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, persistent, ts, s)
 }
 
 hipError_t launch_render_bwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              const float *dl_dimage, const float *final_t,
-                             const int32_t *n_contrib, int persistent, hipStream_t s) {
-    XG_DISPATCH(bwd_t, ws, cams, p, dl_dimage, final_t, n_contrib, persistent, s)
+                             const int32_t *n_contrib, int persistent, const TStore &ts,
+                             hipStream_t s) {
+    XG_DISPATCH(bwd_t, ws, cams, p, dl_dimage, final_t, n_contrib, persistent, ts, s)
 }
 
 hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Params &p,

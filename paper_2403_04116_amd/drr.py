@@ -49,6 +49,18 @@ def _stream(stream) -> int:
     return int(stream.cuda_stream)
 
 
+class TStore:
+    """Stored transmittances between a forward and its backward."""
+
+    def __init__(self, buf: torch.Tensor, view: torch.Tensor, slots: int, tile: int):
+        self.buf, self.view, self.slots, self.tile = buf, view, int(slots), int(tile)
+
+    def contributors(self, frame: "Frame") -> torch.Tensor:
+        """Per-pixel contributor counts written by the forward, in tile order."""
+        n = frame.total_tiles * self.tile * self.tile
+        return self.view[:4 * n].view(torch.int32)
+
+
 class Frame:
     """n Gaussians rendered into a fixed list of views, with its workspace.
 
@@ -167,6 +179,34 @@ class Frame:
         gr = X.XgGrads(*(grads[k].data_ptr() for k in PARAMS))
         s = _stream(stream)
         X.xg_render_bwd(self.frame, dl_dimage.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), s)
+        X.xg_preprocess_bwd(self.frame, gaussians_struct(g), gr, s)
+        return grads
+
+    # -- stored-transmittance variant ------------------------------------------
+    def new_store(self, slots: int) -> "TStore":
+        """A buffer for the transmittances of the first ``slots`` contributors
+        of every pixel (256-byte aligned view of a torch allocation)."""
+        nbytes = X.xg_store_size(self.frame, slots)
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        return TStore(buf, buf[off:off + nbytes], slots, self.settings.tile)
+
+    def render_fwd_store(self, g: dict, store: "TStore", out=None, stream=None):
+        image, final_t, n_contrib = out if out is not None else self.new_outputs()
+        X.xg_render_fwd_store(self.frame, gaussians_struct(g), image.data_ptr(), final_t.data_ptr(),
+                              n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
+                              store.view.numel(), _stream(stream))
+        return image, final_t, n_contrib
+
+    def backward_store(self, g: dict, dl_dimage: torch.Tensor, final_t: torch.Tensor,
+                       n_contrib: torch.Tensor, store: "TStore", grads: dict | None = None,
+                       stream=None) -> dict:
+        grads = self.new_grads(g) if grads is None else grads
+        gr = X.XgGrads(*(grads[k].data_ptr() for k in PARAMS))
+        s = _stream(stream)
+        X.xg_render_bwd_store(self.frame, dl_dimage.data_ptr(), final_t.data_ptr(),
+                              n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
+                              store.view.numel(), s)
         X.xg_preprocess_bwd(self.frame, gaussians_struct(g), gr, s)
         return grads
 

@@ -184,3 +184,33 @@ def test_package_fails_loudly_without_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", "import paper_2403_04116_amd"], cwd=tmp_path,
                        capture_output=True, text=True)
     assert r.returncode != 0 and "not built" in r.stderr
+
+
+def test_store_size_and_validation():
+    f, _ = _frame(views=((64, 64), (40, 24)))
+    px_tiles = (16 + 3 * 2) * 256
+    s8 = X.xg_store_size(f, 8)
+    s9 = X.xg_store_size(f, 9)
+    assert s9 - s8 == px_tiles * 4
+    assert s8 >= px_tiles * 4 * 9 and s8 % 256 == 0
+    for bad in (0, -1, X.MAX_STORE_SLOTS + 1):
+        with pytest.raises(X.XgError) as e:
+            X.xg_store_size(f, bad)
+        assert e.value.status == X.XG_EINVAL
+    # a frame with (fake) device pointers: the store checks fail before any HIP call
+    need = P.xg_workspace_size(f)
+    f.cams_dev = 256
+    f.ws = 256
+    f.ws_bytes = need
+    g = X.XgGaussians(256, 256, 256, 256, 256, 100)
+    for store, slots, nbytes in ((0, 8, s8), (256 + 4, 8, s8), (256, 8, s8 - 256), (256, 0, s8)):
+        with pytest.raises(X.XgError) as e:
+            X.xg_render_fwd_store(f, g, 256, 256, 256, store, slots, nbytes, 0)
+        assert e.value.status == X.XG_EINVAL
+        with pytest.raises(X.XgError) as e:
+            X.xg_render_bwd_store(f, 256, 256, 256, store, slots, nbytes, 0)
+        assert e.value.status == X.XG_EINVAL
+    f.settings.flags = 1           # the persistent queue has no stored variant
+    with pytest.raises(X.XgError) as e:
+        X.xg_render_fwd_store(f, g, 256, 256, 256, 256, 8, s8, 0)
+    assert e.value.status == X.XG_EINVAL
