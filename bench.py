@@ -1,14 +1,20 @@
 """Benchmark: DRR forward + backward views/s, batched vs per-view, one GPU.
 
-Workload: 200 000 radiative Gaussians (log-scales ~ N(log 0.02, 0.3)),
-8 views of 512 x 512 at evenly spaced azimuths, L1 loss against a target
-rendered from a perturbed copy of the scene.  One step = the whole hot path
-for all views: preprocess, tile binning + radix sort, forward blending, L1
-upstream gradient, reverse blending, and the adjoint of the projection to
-every Gaussian parameter.  Inputs are resident in HBM before timing.
+Default workload: 200 000 radiative Gaussians (log-scales ~
+N(log 0.02, 0.3)), 8 views of 512 x 512 at evenly spaced azimuths, L1 loss
+against a target rendered from a perturbed copy of the scene.  One step =
+the whole hot path for all views: preprocess, tile binning + radix sort,
+forward blending, L1 upstream gradient, reverse blending, and the adjoint
+of the projection to every Gaussian parameter.  Inputs are resident in HBM
+before timing.
 
 Batched: all views in one set of launches.  Per-view: the same kernels with
 one view per launch sequence, looped over the views.  Prints one JSON line.
+
+--workload 5 is the training-scale case (1M Gaussians, 16 views of
+512 x 512, anisotropic scales) whose step also runs the fused Adam update;
+--store SLOTS switches to the stored-transmittance forward/backward.  Both
+report the peak device memory of the step.
 """
 from __future__ import annotations
 
@@ -45,6 +51,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--graph", type=int, default=1,
                     help="also time the batched step captured as one HIP graph (1/0)")
+    ap.add_argument("--store", type=int, default=0, metavar="SLOTS",
+                    help="stored-transmittance variant with SLOTS per pixel (0: divide back)")
+    ap.add_argument("--adam", type=int, default=-1,
+                    help="run the fused Adam update in every step (1/0; default: on for workload 5)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run 3 plain device copies of MB MiB (counter calibration)")
     return ap.parse_args()
@@ -72,9 +82,11 @@ def main():
 
     import scenes as S
     import paper_2403_04116_amd as P
+    from paper_2403_04116_amd import _lib as X
 
     dev = torch.device("cuda:0")
     w = S.workload(args.workload)
+    use_adam = (args.workload == 5) if args.adam < 0 else bool(args.adam)
     g_np = S.scene(args.workload)
     tgt_np = S.perturb(g_np, w.seeds["perturb"])
     D = S.DETECTOR_SIDE
@@ -93,10 +105,19 @@ def main():
     del tframe
 
     stream = torch.cuda.current_stream()
+    del gt_t
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
 
     # ---- batched path -------------------------------------------------------
+    opt = None
+    if use_adam:
+        from paper_2403_04116_amd.optim import FusedAdam
+        opt = FusedAdam.from_activated(g)
+        g = opt.act              # the renderer reads the optimiser's activated copies
     frame = P.Frame(w.n, cams, st, device=dev)
     n_pairs = frame.fit_capacity(g)
+    store = frame.new_store(args.store) if args.store > 0 else None
     out = frame.new_outputs()
     dl = torch.empty(npx, dtype=torch.float32, device=dev)
     grads = frame.new_grads(g)
@@ -107,14 +128,19 @@ def main():
     ev = {k: [] for k in ("fwd0", "fwd1", "bwd0", "bwd1")}
 
     def step_batched(record: bool):
-        for t in grads.values():
-            t.zero_()
+        grads.zero_()
         P.xg_preprocess(frame.frame, gs, sid)
         P.xg_bin_sort(frame.frame, sid)
         if record:
             e0 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-        P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
+        if store is None:
+            P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
+                            n_contrib.data_ptr(), sid)
+        else:
+            X.xg_render_fwd_store(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
+                                  n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
+                                  store.view.numel(), sid)
         if record:
             e1 = torch.cuda.Event(enable_timing=True)
             e1.record(stream)
@@ -122,13 +148,20 @@ def main():
         if record:
             e2 = torch.cuda.Event(enable_timing=True)
             e2.record(stream)
-        P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
+        if store is None:
+            P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
+        else:
+            X.xg_render_bwd_store(frame.frame, dl.data_ptr(), final_t.data_ptr(),
+                                  n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
+                                  store.view.numel(), sid)
         if record:
             e3 = torch.cuda.Event(enable_timing=True)
             e3.record(stream)
             ev["fwd0"].append(e0); ev["fwd1"].append(e1)
             ev["bwd0"].append(e2); ev["bwd1"].append(e3)
         P.xg_preprocess_bwd(frame.frame, gs, gr, sid)
+        if opt is not None:
+            opt.step(grads, sid, gate=frame.status_ptr())
 
     def timed(fn, steps, warmup, **kw):
         for _ in range(warmup):
@@ -147,6 +180,11 @@ def main():
 
     ms_batched, wall_b = timed(step_batched, args.steps, args.warmup)
     assert frame.status() == 0, "pair capacity exceeded during timing"
+    hbm = {"peak_allocated": int(torch.cuda.max_memory_allocated()),
+           "workspace": int(frame.ws.numel()),
+           "store": int(store.view.numel()) if store is not None else 0,
+           "optimizer_state": int(opt.m.numel() * 8 + sum(t.numel() * 4 for t in opt.raw.values()))
+           if opt is not None else 0}
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev["fwd0"], ev["fwd1"])]))
     bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev["bwd0"], ev["bwd1"])]))
 
@@ -175,7 +213,7 @@ def main():
     graph = None
     if args.graph:
         from paper_2403_04116_amd.step import TrainStep
-        ts = TrainStep(frame, g, target, scale, grads=grads)
+        ts = TrainStep(frame, g, target, scale, grads=grads, optimizer=opt, store=store)
         ts.capture()
         for _ in range(args.warmup):
             ts.replay()
@@ -194,7 +232,7 @@ def main():
 
     # ---- per-view path ------------------------------------------------------
     per_view = None
-    if not args.no_per_view:
+    if not args.no_per_view and store is None and opt is None:
         frames = []
         off = 0
         for v in range(w.n_views):
@@ -206,8 +244,7 @@ def main():
             off += wv * hv
 
         def step_per_view(record: bool):
-            for t in grads.values():
-                t.zero_()
+            grads.zero_()
             for f, im, ft, nc, d, tg, n in frames:
                 P.xg_preprocess(f.frame, gs, sid)
                 P.xg_bin_sort(f.frame, sid)
@@ -254,8 +291,12 @@ def main():
                "sample": f"{done_views} of {w.n_views} views, each: pair emission + sort, binned "
                          f"forward, target forward, binned adjoint (FP64), {el:.1f} s"}
 
+    if args.workload == 3:
+        metric = "DRR fwd+bwd views/s at 512^2, 200k Gaussians; batched vs per-view, same GPU"
+    else:
+        metric = f"DRR fwd+bwd{'+Adam' if opt is not None else ''} views/s, {w.describe()}"
     res = {
-        "metric": "DRR fwd+bwd views/s at 512^2, 200k Gaussians; batched vs per-view, same GPU",
+        "metric": metric,
         "value": value,
         "unit": "views/s",
         "n_gpus": 1,
@@ -267,10 +308,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.n} Gaussians, {w.n_views} views of 512x512, L1, fwd+bwd",
-                   "gaussians": w.n, "views": w.n_views, "detector": "512x512",
+        "config": {"workload": f"{w.describe()}, L1, fwd+bwd" + ("+Adam" if opt is not None else ""),
+                   "gaussians": w.n, "views": w.n_views,
+                   "detector": "x".join(map(str, w.sizes[0])) if len(set(w.sizes)) == 1 else "mixed",
                    "tile": args.tile, "lds_batch": args.lds, "persistent": bool(args.persistent),
-                   "path": "batched"},
+                   "store_slots": args.store, "adam": opt is not None, "path": "batched"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "launch_ms": dom_ms, "flops_per_launch": dom_flops},
@@ -284,6 +326,7 @@ def main():
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),
         "wall_s": wall_b,
         "kernel_source_hash": kernel_source_hash(),
+        "hbm": hbm,
     }
     print(json.dumps(res))
 

@@ -68,7 +68,7 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 
 struct Plan {
     xg_ws_layout lay;
-    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], hist, hist_tmp, tile_order;
+    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, lookback[2], tile_order;
     int64_t total_px, total_tiles, n_items;
     int32_t item_blocks, pair_blocks, tile_bits, view_bits, pair_passes;
 };
@@ -86,7 +86,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.tile_bits = bits_of(P.total_tiles - 1);
     P.view_bits = bits_of(f->n_views);
     P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
-    const int64_t hist_n = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);
+    const int64_t lb_words = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);
     const int64_t scan_words = (ni + kScanBlock - 1) / kScanBlock + 1;
     const int64_t part_words = 2 * ((ni + 255) / 256) + 2;
     size_t o = 0;
@@ -105,8 +105,8 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     for (int b = 0; b < 2; ++b) { P.ivals[b] = o; o = align_up(o + 4 * (size_t)ni); }
     for (int b = 0; b < 2; ++b) { P.ptile[b] = o; o = align_up(o + 4 * (size_t)cap); }
     for (int b = 0; b < 2; ++b) { P.pval[b] = o; o = align_up(o + 4 * (size_t)cap); }
-    P.hist = o;               o = align_up(o + 4 * (size_t)hist_n);
-    P.hist_tmp = o;           o = align_up(o + 4 * (size_t)((hist_n + kScanBlock - 1) / kScanBlock + 1));
+    P.ghist = o;              o = align_up(o + 4 * (size_t)kSortCtlWords);
+    for (int b = 0; b < 2; ++b) { P.lookback[b] = o; o = align_up(o + 8 * (size_t)lb_words); }
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
     L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
     P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
@@ -132,8 +132,10 @@ Ws resolve(const xg_frame *f, const Plan &P) {
         w.ptile[k] = (uint32_t *)(b + P.ptile[k]);
         w.pval[k] = (uint32_t *)(b + P.pval[k]);
     }
-    w.hist = (uint32_t *)(b + P.hist);
-    w.hist_tmp = (uint32_t *)(b + P.hist_tmp);
+    w.ghist = (uint32_t *)(b + P.ghist);
+    w.pctr = w.ghist + kMaxPasses * kRadix * kGhStride;
+    w.lookback[0] = (uint64_t *)(b + P.lookback[0]);
+    w.lookback[1] = (uint64_t *)(b + P.lookback[1]);
     w.ranges = (uint32_t *)(b + P.lay.ranges);
     w.grad2d = (float *)(b + P.lay.grad2d);
     w.tile_order = (int32_t *)(b + P.tile_order);
@@ -302,7 +304,6 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
         if (e == hipSuccess) e = launch_sort_pairs(ws, s);
     }
     if (e == hipSuccess) e = launch_ranges(ws, s);
-    if (e == hipSuccess) e = launch_tile_order(ws, s);
     return hip_status(e);
 }
 
@@ -314,8 +315,13 @@ xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, 
     if (!valid_gaussians(g, f->n) || !image || !final_t || !n_contrib) return XG_EINVAL;
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
-    return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib,
-                                        (f->settings.flags & XG_F_PERSISTENT) != 0,
+    const bool persistent = (f->settings.flags & XG_F_PERSISTENT) != 0;
+    // the persistent queue's work order, from the current tile ranges
+    if (persistent) {
+        const hipError_t e = launch_tile_order(ws, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib, persistent,
                                         TStore{nullptr, nullptr, 0}, (hipStream_t)stream));
 }
 
@@ -327,8 +333,12 @@ xg_status xg_render_bwd(const xg_frame *f, const float *dl_dimage, const float *
     if (!dl_dimage || !final_t || !n_contrib) return XG_EINVAL;
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
-    return hip_status(launch_render_bwd(ws, f->cams_dev, p, dl_dimage, final_t, n_contrib,
-                                        (f->settings.flags & XG_F_PERSISTENT) != 0,
+    const bool persistent = (f->settings.flags & XG_F_PERSISTENT) != 0;
+    if (persistent) {
+        const hipError_t e = launch_tile_order(ws, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return hip_status(launch_render_bwd(ws, f->cams_dev, p, dl_dimage, final_t, n_contrib, persistent,
                                         TStore{nullptr, nullptr, 0}, (hipStream_t)stream));
 }
 

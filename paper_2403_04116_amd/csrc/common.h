@@ -69,8 +69,9 @@ struct Ws {
     uint32_t *ivals[2];    // item sort values ((view, Gaussian) index)
     uint32_t *ptile[2];    // pair sort keys (global tile id)
     uint32_t *pval[2];     // pair sort values (Gaussian index)
-    uint32_t *hist;
-    uint32_t *hist_tmp;
+    uint32_t *ghist;       // radix sort: digit histograms [kMaxPasses][kRadix], one 128-byte line each
+    uint32_t *pctr;        // radix sort: partition counters [kMaxPasses]
+    uint64_t *lookback[2]; // radix sort: per (partition, digit) aggregate / prefix words
     uint32_t *ranges;
     float *grad2d;
     int32_t *tile_order;   // persistent queue: tiles in work order
@@ -108,6 +109,9 @@ constexpr int kSortItems = 16;
 constexpr int kSortBlock = kSortThreads * kSortItems;   // 4096 pairs
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxPasses = 5;                            // view bits + 32 depth bits, 8 at a time
+constexpr int kGhStride = 32;   // words between histogram bins (spreads their atomics over channels)
+constexpr int kSortCtlWords = (kMaxPasses * kRadix + kMaxPasses) * kGhStride;
 
 // ---- launchers (one translation unit per stage) --------------------------
 hipError_t launch_reset(const Ws &ws, hipStream_t s);

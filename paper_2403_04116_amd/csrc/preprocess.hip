@@ -255,32 +255,72 @@ __global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_
 // Duplicate-with-key, in depth order: item j of the depth-sorted items
 // writes one (global tile id, Gaussian index) pair per tile of its
 // rectangle at its scanned offset.  A stable sort of these pairs by tile
-// then leaves every tile's list in (depth, index) order.  Pairs past the
-// capacity are dropped (the scan has raised XG_ECAPACITY).
+// then leaves every tile's list in (depth, index) order.  Nothing is
+// written once the scan has raised XG_ECAPACITY (the later stages then see
+// no pairs), so every offset is below the capacity.
+//
+// The pairs of a workgroup's 256 consecutive items form one contiguous
+// range; when it fits, they are assembled in LDS and written as whole
+// lines, else each item writes its own.
+constexpr int kEmitStage = 4096;
+
 __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int tile) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ws.n_items) return;
-    const uint32_t cnt = ws.icounts[j];
-    if (cnt == 0) return;
-    const uint32_t off = ws.offsets[j];
-    if ((int64_t)off + cnt > ws.cap) return;
-    const uint32_t idx = ws.ivals[ws.hdr->item_sel & 1][j];
-    const int v = (int)(idx / (uint32_t)ws.n);
-    const uint32_t i = idx - (uint32_t)v * (uint32_t)ws.n;
-    const int4 rc = ws.rec[idx].c;
-    const xg_camera &c = cams[v];
-    const int txn = (c.width + tile - 1) / tile;
-    const int tx0 = (rc.z & 0xffff) / tile, tx1 = (rc.z >> 16) / tile;
-    const int ty0 = (rc.w & 0xffff) / tile, ty1 = (rc.w >> 16) / tile;
-    uint32_t *tt = ws.ptile[0] + off;
-    uint32_t *vv = ws.pval[0] + off;
-    int m = 0;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            tt[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
-            vv[m] = i;
-            ++m;
+    __shared__ uint32_t s_t[kEmitStage];
+    __shared__ uint32_t s_v[kEmitStage];
+    __shared__ uint32_t s_range[2];
+    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x;
+    if (j0 >= ws.n_items || ws.hdr->status != XG_OK) return;
+    const int64_t j = j0 + threadIdx.x;
+    const int64_t jl = min(j0 + (int64_t)blockDim.x, ws.n_items) - 1;   // last item of the block
+    if (threadIdx.x == 0) {
+        s_range[0] = ws.offsets[j0];
+        s_range[1] = ws.offsets[jl] + ws.icounts[jl];
+    }
+    uint32_t cnt = 0, off = 0;
+    uint32_t idx = 0;
+    if (j < ws.n_items) {
+        cnt = ws.icounts[j];
+        off = ws.offsets[j];
+        idx = ws.ivals[ws.hdr->item_sel & 1][j];
+    }
+    __syncthreads();
+    const uint32_t base = s_range[0];
+    const uint32_t total = s_range[1] - base;
+    const bool staged = total <= (uint32_t)kEmitStage;
+    if (cnt > 0) {
+        const int v = (int)(idx / (uint32_t)ws.n);
+        const uint32_t i = idx - (uint32_t)v * (uint32_t)ws.n;
+        const int4 rc = ws.rec[idx].c;
+        const xg_camera &c = cams[v];
+        const int txn = (c.width + tile - 1) / tile;
+        const int tx0 = (rc.z & 0xffff) / tile, tx1 = (rc.z >> 16) / tile;
+        const int ty0 = (rc.w & 0xffff) / tile, ty1 = (rc.w >> 16) / tile;
+        if (staged) {
+            uint32_t m = off - base;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    s_t[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
+                    s_v[m] = i;
+                    ++m;
+                }
+        } else {
+            uint32_t *tt = ws.ptile[0] + off;
+            uint32_t *vv = ws.pval[0] + off;
+            int m = 0;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    tt[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
+                    vv[m] = i;
+                    ++m;
+                }
         }
+    }
+    if (!staged) return;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < total; k += blockDim.x) {
+        ws.ptile[0][base + k] = s_t[k];
+        ws.pval[0][base + k] = s_v[k];
+    }
 }
 
 // Adjoint of the projection for one Gaussian, summed over views.
@@ -290,16 +330,22 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
 // With power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 and [[A, B], [B, C]] the
 // inverse 2-D covariance: dL/du = [[A, B], [B, C]] (sum g d),
 // dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy, dL/dC = -sum g dy^2 / 2.
+//
+// L lanes share one Gaussian (views sub, sub + L, ...) and sum their
+// partial gradients with lane shuffles, so a launch has n * L threads.
+template <int L>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
                                                         Params p, xg_grads gr) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ws.n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / L);
+    const int sub = (int)(t % L);
+    if (i >= ws.n) return;     // whole groups of L lanes leave together
     const float *m = g.means + 3 * (int64_t)i;
     const float *s = g.scales + 3 * (int64_t)i;
     const float *q = g.quats + 4 * (int64_t)i;
     double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0, gi = 0;
     bool any = false;
-    for (int v = 0; v < ws.n_views; ++v) {
+    for (int v = sub; v < ws.n_views; v += L) {
         const int64_t idx = (int64_t)v * ws.n + i;
         if (ws.counts[idx] == 0) continue;
         const float4 g0 = reinterpret_cast<const float4 *>(ws.grad2d)[2 * idx];
@@ -385,7 +431,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
 #pragma unroll
         for (int a = 0; a < 3; ++a) gm[a] += r[a] * gtx + r[3 + a] * gty + r[6 + a] * gtz;
     }
-    if (!any) return;
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gm[a] += __shfl_xor(gm[a], o, kWave);
+            gs[a] += __shfl_xor(gs[a], o, kWave);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) gq[a] += __shfl_xor(gq[a], o, kWave);
+        go += __shfl_xor(go, o, kWave);
+        gi += __shfl_xor(gi, o, kWave);
+        any = __shfl_xor((int)any, o, kWave) != 0 || any;
+    }
+    if (!any || sub != 0) return;
     float *om = gr.means + 3 * (int64_t)i;
     float *os = gr.scales + 3 * (int64_t)i;
     float *oq = gr.quats + 4 * (int64_t)i;
@@ -448,8 +507,17 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
 
 hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                                  const Params &p, const xg_grads &gr, hipStream_t s) {
-    const int nb = (ws.n + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, ws, g, cams, p, gr);
+    // one lane per Gaussian measured fastest (spreading the views over 2-8
+    // lanes made the launch slower); the shuffled variants stay available
+    const int L = 1;
+    const int64_t nb = ((int64_t)ws.n * L + 255) / 256;
+    const dim3 grid((unsigned)(nb > 0 ? nb : 1));
+    switch (L) {
+        case 8: hipLaunchKernelGGL(k_preprocess_bwd<8>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
+        case 4: hipLaunchKernelGGL(k_preprocess_bwd<4>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
+        case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
+        default: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
+    }
     return hipGetLastError();
 }
 

@@ -80,12 +80,47 @@ __device__ __forceinline__ uint32_t subblock_mask(int xl, int xh, int yl, int yh
     return m;
 }
 
+// Smallest value over the box [X0, X1] x [Y0, Y1] of the exponent
+// E(dx, dy) = (qa dx + qb dy)^2 + (qc dy)^2 (qa > 0, qb^2 + qc^2 > 0):
+// zero when the box holds the centre, else the least of the minima along
+// its four edges (each a one-dimensional quadratic, clamped to the edge).
+__device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, float X0, float X1,
+                                                  float Y0, float Y1) {
+    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
+    float best = __builtin_inff();
+    const float ys[2] = {Y0, Y1};
+    const float xs[2] = {X0, X1};
+    // approximate reciprocals: an argmin off by a rounding error raises the
+    // minimum by a second-order amount, far inside the caller's margin
+    const float rx = qb * __builtin_amdgcn_rcpf(qa);
+    const float ry = qa * qb * __builtin_amdgcn_rcpf(qb * qb + qc * qc);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float Y = ys[k];
+        const float x = fminf(fmaxf(-rx * Y, X0), X1);
+        const float e1 = qa * x + qb * Y, e2 = qc * Y;
+        best = fminf(best, e1 * e1 + e2 * e2);
+        const float X = xs[k];
+        const float y = fminf(fmaxf(-ry * X, Y0), Y1);
+        const float f1 = qa * X + qb * y, f2 = qc * y;
+        best = fminf(best, f1 * f1 + f2 * f2);
+    }
+    return best;
+}
+
 // Stages list entries [b0, b0 + cnt) of the tile into LDS, with the mask of
-// the 8 x 8 sub-blocks each entry's rectangle touches.
-template <int T, int NT>
+// the 8 x 8 sub-blocks each entry must be visited for.  A sub-block is in
+// the mask when the entry's rectangle touches it and (CULL) the entry's
+// alpha can reach alpha_min somewhere in that part of the rectangle: the
+// smallest exponent over the part, a lower bound of every pixel's, is
+// compared with log2(o / alpha_min) plus a margin far above float
+// rounding.  Dropping the others skips only evaluations that the
+// per-pixel alpha test would skip, so results do not change.
+template <int T, int NT, bool CULL>
 __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32_t b0, int cnt,
-                                      const TileGeom &tg, float4 *s_a, float4 *s_b,
+                                      const TileGeom &tg, float amin, float4 *s_a, float4 *s_b,
                                       uint16_t *s_mask, uint32_t *s_rid) {
+    constexpr int SB = T / 8;
     for (int k = threadIdx.x; k < cnt; k += NT) {
         const uint32_t gi = vals[b0 + k];
         const int64_t rid = (int64_t)tg.view * ws.n + gi;
@@ -100,17 +135,30 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         const uint32_t rect = (uint32_t)xl | ((uint32_t)xh << 8) | ((uint32_t)yl << 16) | ((uint32_t)yh << 24);
         s_a[k] = make_float4(ux, uy, ra.z, ra.w);
         s_b[k] = make_float4(rb.x, rb.y, rb.z, __uint_as_float(rect));
-        if (T > 8) s_mask[k] = (uint16_t)subblock_mask<T / 8>(xl, xh, yl, yh);
+        uint32_t m = subblock_mask<SB>(xl, xh, yl, yh);
+        if (CULL) {
+            const float thr = __builtin_amdgcn_logf(rb.y * __builtin_amdgcn_rcpf(amin)) * 1.00001f + 1e-3f;
+            // pixel centres relative to the Gaussian centre
+            const float ox = (float)(tg.x0 - tg.rx) + 0.5f - ux;
+            const float oy = (float)(tg.y0 - tg.ry) + 0.5f - uy;
+#pragma unroll
+            for (int sb = 0; sb < SB * SB; ++sb) {
+                if (!((m >> sb) & 1u)) continue;
+                const int bx = (sb % SB) * 8, by = (sb / SB) * 8;
+                const float X0 = ox + (float)max(xl, bx), X1 = ox + (float)min(xh, bx + 7);
+                const float Y0 = oy + (float)max(yl, by), Y1 = oy + (float)min(yh, by + 7);
+                if (box_min_exponent(ra.z, ra.w, rb.x, X0, X1, Y0, Y1) > thr) m &= ~(1u << sb);
+            }
+        }
+        s_mask[k] = (uint16_t)m;
         if (s_rid) s_rid[k] = (uint32_t)rid;
     }
 }
 
 // Compacts, in list order, the staged entries [0, cnt) whose rectangle
 // touches this wavefront's sub-block w into list[]; returns their number
-// (wavefront-uniform).  A tile of one 8 x 8 block needs no list.
-template <int NW>
+// (wavefront-uniform).
 __device__ __forceinline__ int wave_list(const uint16_t *s_mask, int cnt, int w, uint16_t *list) {
-    if (NW == 1) return cnt;
     const int lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
     int n = 0;
@@ -131,8 +179,8 @@ struct BlendLds {
     float4 a[B];
     float4 b[B];
     uint32_t rid[B];
-    uint16_t mask[T > 8 ? B : 1];
-    uint16_t list[NW > 1 ? NW : 1][NW > 1 ? B : 1];
+    uint16_t mask[B];
+    uint16_t list[NW][B];
     int wmax[NW];
     int next;
 };
@@ -163,7 +211,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     const uint32_t e = ws.ranges[2 * (int64_t)tile + 1];
     const uint32_t *vals = ws.pval[ws.pair_sel];
     const float amin = p.alpha_min, amax = p.alpha_max, tmin = p.t_min;
-    uint16_t *list = sh.list[NW > 1 ? w : 0];
+    uint16_t *list = sh.list[w];
 
     float Tr = 1.0f, C = 0.0f;
     int last = 0;
@@ -174,12 +222,14 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     for (uint32_t b0 = s; b0 < e; b0 += B) {
         const int cnt = (int)min((uint32_t)B, e - b0);
         if (!__syncthreads_or(!done)) break;
-        stage<T, NT>(ws, vals, b0, cnt, tg, s_a, s_b, s_mask, nullptr);
+        // the counting variant keeps every rectangle evaluation (the work
+        // count of the definition), the others skip sub-blocks out of reach
+        stage<T, NT, !COUNT>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr);
         __syncthreads();
         if (!__any(!done)) continue;
-        const int nl = wave_list<NW>(s_mask, cnt, w, list);
+        const int nl = wave_list(s_mask, cnt, w, list);
         for (int j = 0; j < nl; ++j) {
-            const int k = (NW > 1) ? (int)list[j] : j;
+            const int k = (int)list[j];
             const float4 sa = s_a[k];
             const float4 sb = s_b[k];
             const uint32_t rect = __float_as_uint(sb.w);
@@ -340,7 +390,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
     const uint32_t *vals = ws.pval[ws.pair_sel];
     const float amin = p.alpha_min, amax = p.alpha_max;
-    uint16_t *list = sh.list[NW > 1 ? w : 0];
+    uint16_t *list = sh.list[w];
 
     float g = 0.0f, Tr = 1.0f;
     int last = 0;
@@ -376,12 +426,12 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         const int b0 = max(end - B, 0);
         const int cnt = end - b0;
         __syncthreads();
-        stage<T, NT>(ws, vals, s + (uint32_t)b0, cnt, tg, s_a, s_b, s_mask, s_rid);
+        stage<T, NT, true>(ws, vals, s + (uint32_t)b0, cnt, tg, amin, s_a, s_b, s_mask, s_rid);
         __syncthreads();
         if (b0 >= wmax) continue;
-        const int nl = wave_list<NW>(s_mask, min(cnt, wmax - b0), w, list);
+        const int nl = wave_list(s_mask, min(cnt, wmax - b0), w, list);
         for (int j = nl - 1; j >= 0; --j) {
-            const int k = (NW > 1) ? (int)list[j] : j;
+            const int k = (int)list[j];
             const float4 sa = s_a[k];
             const float4 sb = s_b[k];
             const int pos1 = b0 + k + 1;

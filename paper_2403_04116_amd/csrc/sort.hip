@@ -11,11 +11,16 @@
 // exactly the order of a sort on (tile << 32 | depth bits, index), while
 // the bulky pass over pairs moves 8-byte records on tile bits only.
 //
-// A pass is: per-block digit histograms -> exclusive scan of the
-// digit-major histogram matrix (global offsets) -> scatter.  The scatter
-// ranks keys stably inside a 4096-key block with wavefront ballots, stages
-// them digit-sorted in LDS and writes each digit's run contiguously.
-// Item passes beyond the varying bits return at once (the header records
+// Each sort is one histogram launch (the digit counts of every pass in one
+// read of the keys) and one launch per 8-bit pass, in the single-pass
+// ("onesweep") form: a workgroup takes the next 4096-key partition from an
+// atomic counter, ranks its keys stably with wavefront ballots, publishes
+// its per-digit counts, and reads the running prefix of the partitions
+// before it from their published words (decoupled look-back: a partition
+// waits only on ones that started before it, so it always finishes); it
+// then stages its keys digit-sorted in LDS and writes each digit's run
+// contiguously.  Item passes past the varying bits, or whose digit is the
+// same for every key, are skipped without moving data (the header records
 // which buffer holds the result), so launch sequences are data independent.
 #include "common.h"
 
@@ -50,8 +55,10 @@ struct ItemSort {
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ikeys[b]; }
     static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.ivals[b]; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
-    static __device__ __forceinline__ void done(const Ws &ws, int pass) {
-        ws.hdr->item_sel = (pass + 1) & 1;
+    static constexpr bool kSkipConstant = true;
+    // the result sits in buffer (passes that moved data) & 1
+    static __device__ __forceinline__ void done(const Ws &ws, int nrun) {
+        ws.hdr->item_sel = nrun & 1;
     }
 };
 
@@ -74,37 +81,93 @@ struct PairSort {
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ptile[b]; }
     static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.pval[b]; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
+    // every pass runs, so the result buffer (pair_passes & 1) is known on the host
+    static constexpr bool kSkipConstant = false;
     static __device__ __forceinline__ void done(const Ws &, int) {}
 };
 
+// Look-back words: flag in bits 62-63, count in the low 32 bits.
+constexpr uint64_t kLbAggregate = 1ull << 62;   // this partition's own digit count
+constexpr uint64_t kLbPrefix = 2ull << 62;      // inclusive prefix through this partition
+// Polls of a predecessor's word before a partition gives up (it never has
+// to in a correct launch: predecessors publish before they wait); the sort
+// then reports XG_EHIP through the status word instead of hanging.
+constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr int kLookback = 16;    // predecessors read per look-back step
+
+// Zeroes the digit histograms, partition counters and the first pass's
+// look-back words of one sort.
 template <class S>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(Ws ws, int pass) {
+__global__ __launch_bounds__(256) void k_sort_prep(Ws ws) {
     const Ctl c = S::ctl(ws);
-    const int shift = pass * kRadixBits;
-    if (shift >= c.total_bits) return;
-    __shared__ uint32_t hist[kRadix];
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-    const typename S::Key *in = S::keys(ws, pass & 1);
-    const int64_t base = (int64_t)blockIdx.x * kSortBlock;
-#pragma unroll 4
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t j = base + (int64_t)k * kSortThreads + threadIdx.x;
-        if (j < c.n) atomicAdd(&hist[S::digit(in[j], c, shift)], 1u);
-    }
-    __syncthreads();
-    ws.hist[(int64_t)threadIdx.x * S::blocks(ws) + blockIdx.x] = hist[threadIdx.x];
+    const int64_t parts = (c.n + kSortBlock - 1) / kSortBlock;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < kSortCtlWords; i += stride) ws.ghist[i] = 0;
+    for (int64_t i = i0; i < parts * kRadix; i += stride) ws.lookback[0][i] = 0;
 }
 
+// Lanes of the wavefront whose digit equals this lane's (one ballot per
+// digit bit), restricted to `valid` lanes.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Digit histograms of every pass in one read of the keys: per-wavefront
+// LDS counters (plain LDS atomics), summed per workgroup into the global
+// bins.  A grid of a few workgroups per CU strides over the keys, so each
+// global bin receives few atomics.
 template <class S>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Ws ws, int pass) {
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Ws ws, int passes) {
+    using Key = typename S::Key;
+    constexpr int NW = kSortThreads / kWave;
+    const Ctl c = S::ctl(ws);
+    __shared__ uint32_t hist[NW][kMaxPasses][kRadix];
+    const int w = threadIdx.x / kWave;
+    for (int q = 0; q < kMaxPasses; ++q)
+        for (int k = 0; k < NW; ++k) hist[k][q][threadIdx.x] = 0;
+    __syncthreads();
+    const Key *in = S::keys(ws, 0);
+    for (int64_t base = (int64_t)blockIdx.x * kSortBlock; base < c.n;
+         base += (int64_t)gridDim.x * kSortBlock) {
+        // all loads first (indices clamped into range), then the counting
+        Key key[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t j = base + (int64_t)k * kSortThreads + threadIdx.x;
+            key[k] = in[j < c.n ? j : c.n - 1];
+        }
+        for (int q = 0; q < passes; ++q) {
+            if (q * kRadixBits >= c.total_bits) break;
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) {
+                const int64_t j = base + (int64_t)k * kSortThreads + threadIdx.x;
+                if (j < c.n) atomicAdd(&hist[w][q][S::digit(key[k], c, q * kRadixBits)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < passes; ++q) {
+        uint32_t h = 0;
+        for (int k = 0; k < NW; ++k) h += hist[k][q][threadIdx.x];
+        if (h) atomicAdd(&ws.ghist[(q * kRadix + threadIdx.x) * kGhStride], h);
+    }
+}
+
+// One stable LSD pass on digit `pass` of `passes` launched.
+template <class S>
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int passes) {
     using Key = typename S::Key;
     const Ctl c = S::ctl(ws);
     const int shift = pass * kRadixBits;
-    if (shift >= c.total_bits) return;
-    const int64_t base = (int64_t)blockIdx.x * kSortBlock;
-    if (blockIdx.x == 0 && threadIdx.x == 0) S::done(ws, pass);
-    if (base >= c.n) return;
+    const int64_t parts = (c.n + kSortBlock - 1) / kSortBlock;
 
     __shared__ Key skeys[kSortBlock];
     __shared__ uint32_t svals[kSortBlock];
@@ -112,34 +175,62 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Ws ws, int pass)
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t goff[kRadix];
     __shared__ uint32_t scan_lds[kSortThreads / kWave + 1];
+    __shared__ int s_part;
+
+    // The look-back words of the next pass are cleared here (this pass does
+    // not use them; the previous pass, which did, has finished).
+    {
+        uint64_t *next = ws.lookback[(pass + 1) & 1];
+        const int64_t slot = blockIdx.x;
+        if (slot < parts) next[slot * kRadix + threadIdx.x] = 0;
+    }
+
+    // Which passes move data: those inside the key's bits, and (items) whose
+    // digit is not the same for every key.  Every workgroup derives the same
+    // plan from the histograms.
+    int nrun_before = 0, nrun_total = 0;
+    bool run_this = false;
+    for (int q = 0; q < passes; ++q) {
+        bool run = q * kRadixBits < c.total_bits && c.n > 0;
+        if (run && S::kSkipConstant) run = !__syncthreads_or(ws.ghist[(q * kRadix + threadIdx.x) * kGhStride] == (uint32_t)c.n);
+        if (run && q < pass) ++nrun_before;
+        if (q == pass) run_this = run;
+        if (run) ++nrun_total;
+    }
+    const int in_sel = S::kSkipConstant ? (nrun_before & 1) : (pass & 1);
+    if (pass == passes - 1 && blockIdx.x == 0 && threadIdx.x == 0) S::done(ws, nrun_total);
+    if (!run_this) return;
+
+    if (threadIdx.x == 0) s_part = (int)atomicAdd(&ws.pctr[pass * kGhStride], 1u);
+    for (int k = 0; k < kSortThreads / kWave; ++k) whist[k][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t part = s_part;
+    if (part >= parts) return;
+    const int64_t base = part * kSortBlock;
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    for (int k = 0; k < kSortThreads / kWave; ++k) whist[k][threadIdx.x] = 0;
-    __syncthreads();
-
-    const Key *kin = S::keys(ws, pass & 1);
-    const uint32_t *vin = S::vals(ws, pass & 1);
+    const Key *kin = S::keys(ws, in_sel);
+    const uint32_t *vin = S::vals(ws, in_sel);
     Key key[kSortItems];
     uint32_t val[kSortItems];
     uint32_t rank[kSortItems];
     const int64_t wbase = base + (int64_t)w * (kSortBlock / (kSortThreads / kWave));
+    // all loads first (indices clamped into range), so they overlap
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t j = wbase + (int64_t)r * kWave + lane;
+        const int64_t jc = j < c.n ? j : c.n - 1;
+        key[r] = kin[jc];
+        val[r] = vin[jc];
+    }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t j = wbase + (int64_t)r * kWave + lane;
         const bool valid = j < c.n;
-        key[r] = valid ? kin[j] : (Key)0;
-        val[r] = valid ? vin[j] : 0u;
         const uint32_t d = S::digit(key[r], c, shift);
-        // lanes holding the same digit, via one ballot per digit bit
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
+        const uint64_t peers = digit_peers(d, valid);
         uint32_t old = 0;
         const int leader = __ffsll((unsigned long long)peers) - 1;
         if (valid && lane == leader) old = atomicAdd(&whist[w][d], (uint32_t)__popcll(peers));
@@ -148,7 +239,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Ws ws, int pass)
     }
     __syncthreads();
     {
-        // per digit: prefix over waves, block-local digit start, global offset
         const int d = threadIdx.x;
         uint32_t acc = 0;
 #pragma unroll
@@ -157,9 +247,62 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Ws ws, int pass)
             whist[k][d] = acc;
             acc += t;
         }
+        uint64_t *lb = ws.lookback[pass & 1];
+        uint64_t *mine = lb + part * kRadix + d;
+        // publish this partition's count, then add up the predecessors'
+        if (part == 0) {
+            __hip_atomic_store(mine, kLbPrefix | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(mine, kLbAggregate | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // Look back over a window of kLookback predecessors at a time (their
+        // words are loaded together): add aggregates until a prefix; a
+        // predecessor that has not published yet is polled again.
+        uint32_t excl = 0;
+        bool failed = false;
+        uint32_t spins = 0;
+        for (int64_t q = part - 1; q >= 0;) {
+            uint64_t word[kLookback];
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k)
+                word[k] = (q - k >= 0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : kLbPrefix;     // before partition 0: prefix 0
+            int used = 0;
+            bool stop = false, wait = false;
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k) {
+                if (stop || wait) continue;
+                const uint64_t flag = word[k] & (3ull << 62);
+                if (flag == 0) {
+                    wait = true;
+                } else {
+                    excl += (uint32_t)word[k];
+                    ++used;
+                    stop = flag == kLbPrefix;
+                }
+            }
+            if (stop) break;
+            q -= used;
+            if (wait) {
+                if (++spins > kSpinLimit) {
+                    failed = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (part != 0)
+            __hip_atomic_store(mine, kLbPrefix | (uint32_t)(excl + acc), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (failed) __hip_atomic_store(&ws.hdr->status, (int32_t)XG_EHIP, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        // global start of digit d: keys with smaller digits, then this digit's
+        // keys in earlier partitions
         uint32_t tot;
+        const uint32_t dstart = block_excl_scan(ws.ghist[(pass * kRadix + d) * kGhStride], scan_lds, &tot);
+        goff[d] = dstart + excl;
         bstart[d] = block_excl_scan(acc, scan_lds, &tot);
-        goff[d] = ws.hist[(int64_t)d * S::blocks(ws) + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -174,8 +317,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Ws ws, int pass)
     }
     __syncthreads();
     const int64_t nvalid = min((int64_t)kSortBlock, c.n - base);
-    Key *kout = S::keys(ws, (pass + 1) & 1);
-    uint32_t *vout = S::vals(ws, (pass + 1) & 1);
+    Key *kout = S::keys(ws, in_sel ^ 1);
+    uint32_t *vout = S::vals(ws, in_sel ^ 1);
 #pragma unroll 4
     for (int k = 0; k < kSortItems; ++k) {
         const int pos = k * kSortThreads + threadIdx.x;
@@ -183,8 +326,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Ws ws, int pass)
             const Key kk = skeys[pos];
             const uint32_t d = S::digit(kk, c, shift);
             const uint32_t dst = goff[d] + (uint32_t)pos - bstart[d];
-            kout[dst] = kk;
-            vout[dst] = svals[pos];
+            if (dst < (uint64_t)c.n) {   // always true unless a look-back gave up
+                kout[dst] = kk;
+                vout[dst] = svals[pos];
+            }
         }
     }
 }
@@ -260,13 +405,13 @@ __global__ __launch_bounds__(1024) void k_tile_order(Ws ws) {
 template <class S>
 hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s) {
     const unsigned nb = (unsigned)(blocks > 0 ? blocks : 1);
-    for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_hist<S>, dim3(nb), dim3(kSortThreads), 0, s, ws, p);
-        hipError_t e = launch_scan(ws.hist, ws.hist, (int64_t)kRadix * nb, ws.hist_tmp, nullptr,
-                                   nullptr, 0, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<S>, dim3(nb), dim3(kSortThreads), 0, s, ws, p);
-    }
+    unsigned np = (unsigned)(((int64_t)blocks * kRadix + 255) / 256);
+    if (np > 2048) np = 2048;
+    hipLaunchKernelGGL(k_sort_prep<S>, dim3(np > 0 ? np : 1), dim3(256), 0, s, ws);
+    const unsigned nh = nb < 512 ? nb : 512;
+    hipLaunchKernelGGL(k_sort_hist<S>, dim3(nh), dim3(kSortThreads), 0, s, ws, passes);
+    for (int p = 0; p < passes; ++p)
+        hipLaunchKernelGGL(k_onesweep<S>, dim3(nb), dim3(kSortThreads), 0, s, ws, p, passes);
     return hipGetLastError();
 }
 
@@ -278,6 +423,7 @@ hipError_t launch_sort_items(const Ws &ws, hipStream_t s) {
     hipLaunchKernelGGL(k_item_keys, dim3(grid256(ws.n_items)), dim3(256), 0, s, ws);
     // worst case: view bits + 32 depth bits; passes past the varying bits return at once
     const int passes = (ws.view_bits + 32 + kRadixBits - 1) / kRadixBits;
+    if (passes > kMaxPasses) return hipErrorInvalidValue;
     return radix_passes<ItemSort>(ws, passes, ws.item_blocks, s);
 }
 
@@ -287,6 +433,7 @@ hipError_t launch_gather_counts(const Ws &ws, hipStream_t s) {
 }
 
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s) {
+    if (ws.pair_passes > kMaxPasses) return hipErrorInvalidValue;
     return radix_passes<PairSort>(ws, ws.pair_passes, ws.pair_blocks, s);
 }
 

@@ -49,6 +49,26 @@ def _stream(stream) -> int:
     return int(stream.cuda_stream)
 
 
+class Grads(dict):
+    """Gradient tensors of the Gaussian parameters as views of one flat
+    buffer, so clearing them is a single fill (``zero_()``)."""
+
+    @staticmethod
+    def like(g: dict) -> "Grads":
+        sizes = [g[k].numel() for k in PARAMS]
+        flat = torch.zeros(sum(sizes), dtype=torch.float32, device=g["means"].device)
+        out = Grads()
+        off = 0
+        for k, n in zip(PARAMS, sizes):
+            out[k] = flat[off:off + n].view(g[k].shape)
+            off += n
+        out.flat = flat
+        return out
+
+    def zero_(self) -> None:
+        self.flat.zero_()
+
+
 class TStore:
     """Stored transmittances between a forward and its backward."""
 
@@ -168,8 +188,8 @@ class Frame:
         self.preprocess_sort(g, stream)
         return self.render_fwd(g, out, stream)
 
-    def new_grads(self, g: dict) -> dict:
-        return {k: torch.zeros_like(g[k]) for k in PARAMS}
+    def new_grads(self, g: dict) -> "Grads":
+        return Grads.like(g)
 
     def backward(self, g: dict, dl_dimage: torch.Tensor, final_t: torch.Tensor,
                  n_contrib: torch.Tensor, grads: dict | None = None, stream=None) -> dict:

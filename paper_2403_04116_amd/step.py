@@ -21,7 +21,8 @@ from .drr import PARAMS, Frame, gaussians_struct
 
 class TrainStep:
     def __init__(self, frame: Frame, g: dict, target: torch.Tensor, scale: float,
-                 grads: dict | None = None, zero_grads: bool = True, optimizer=None):
+                 grads: dict | None = None, zero_grads: bool = True, optimizer=None,
+                 store=None):
         self.frame = frame
         self.g = g
         self.target = target
@@ -35,6 +36,8 @@ class TrainStep:
         # FusedAdam over the Gaussians in ``g`` (its activated copies are ``g``);
         # gated by the frame's status word, so an overflowed step changes nothing
         self.optimizer = optimizer
+        # stored-transmittance variant: a Frame.new_store() buffer (None = divide back)
+        self.store = store
 
     def run(self, stream=None, optimize: bool = True) -> None:
         """Enqueues one step on ``stream`` (default: the current stream);
@@ -44,16 +47,30 @@ class TrainStep:
         gs = gaussians_struct(self.g)
         gr = X.XgGrads(*(self.grads[k].data_ptr() for k in PARAMS))
         if self.zero_grads:
-            for t in self.grads.values():
-                t.zero_()
+            if hasattr(self.grads, "flat"):
+                self.grads.zero_()
+            else:
+                for t in self.grads.values():
+                    t.zero_()
         X.xg_preprocess(f.frame, gs, s)
         X.xg_bin_sort(f.frame, s)
-        X.xg_render_fwd(f.frame, gs, self.image.data_ptr(), self.final_t.data_ptr(),
-                        self.n_contrib.data_ptr(), s)
+        st = self.store
+        if st is None:
+            X.xg_render_fwd(f.frame, gs, self.image.data_ptr(), self.final_t.data_ptr(),
+                            self.n_contrib.data_ptr(), s)
+        else:
+            X.xg_render_fwd_store(f.frame, gs, self.image.data_ptr(), self.final_t.data_ptr(),
+                                  self.n_contrib.data_ptr(), st.view.data_ptr(), st.slots,
+                                  st.view.numel(), s)
         X.xg_l1_grad(self.image.data_ptr(), self.target.data_ptr(), self.dl.data_ptr(),
                      self.image.numel(), self.scale, s)
-        X.xg_render_bwd(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
-                        self.n_contrib.data_ptr(), s)
+        if st is None:
+            X.xg_render_bwd(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
+                            self.n_contrib.data_ptr(), s)
+        else:
+            X.xg_render_bwd_store(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
+                                  self.n_contrib.data_ptr(), st.view.data_ptr(), st.slots,
+                                  st.view.numel(), s)
         X.xg_preprocess_bwd(f.frame, gs, gr, s)
         if optimize and self.optimizer is not None:
             self.optimizer.step(self.grads, s, gate=f.status_ptr())
