@@ -178,13 +178,15 @@ xg_status xg_preprocess(const xg_frame *f /* [host] */, const xg_gaussians *g /*
                         void *stream);
 
 /* Stage 2 (Sec. 3.2): the per-tile lists of Gaussians sorted by camera
- * depth.  The (view, Gaussian) items are radix-sorted stably by (view,
- * depth) on the depth bits that vary; their tile counts are scanned in
- * that order; one (global tile id, Gaussian index) pair is emitted per
- * (view, Gaussian, tile) in that order; and the pairs are radix-sorted
- * stably by tile id.  The result equals a sort of the keys
- * (tile << 32 | float32 bits of the depth), ties by ascending Gaussian
- * index.  Also fills per-tile [start, end) ranges. */
+ * depth.  The (view, Gaussian) items are radix-sorted stably by depth on
+ * the depth bits that vary; their tile counts are scanned in that order;
+ * one (global tile id, Gaussian index) pair is emitted per (view,
+ * Gaussian, tile) in that order; and the pairs are radix-sorted stably by
+ * tile id.  A tile lists only Gaussians of its own view, so the result
+ * equals a sort of the keys (tile << 32 | float32 bits of the depth), ties
+ * by ascending Gaussian index.  Also fills per-tile [start, end) ranges.
+ * A sort whose partitions cannot complete reports XG_EHIP in the status
+ * word. */
 xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
 
 /* Stage 3 (Eq. 10): front-to-back blending of every pixel over its tile's

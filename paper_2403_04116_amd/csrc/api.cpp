@@ -70,7 +70,7 @@ struct Plan {
     xg_ws_layout lay;
     size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, lookback[2], tile_order;
     int64_t total_px, total_tiles, n_items;
-    int32_t item_blocks, pair_blocks, tile_bits, view_bits, pair_passes;
+    int32_t item_blocks, pair_blocks, tile_bits, pair_passes;
 };
 
 int bits_of(int64_t v) { return v <= 0 ? 0 : 64 - __builtin_clzll((unsigned long long)v); }
@@ -84,7 +84,6 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.item_blocks = (int32_t)((ni + kSortBlock - 1) / kSortBlock);
     P.pair_blocks = (int32_t)((cap + kSortBlock - 1) / kSortBlock);
     P.tile_bits = bits_of(P.total_tiles - 1);
-    P.view_bits = bits_of(f->n_views);
     P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
     const int64_t lb_words = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);
     const int64_t scan_words = (ni + kScanBlock - 1) / kScanBlock + 1;
@@ -101,7 +100,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.icounts = o;            o = align_up(o + 4 * (size_t)ni);
     L.offsets = o;            o = align_up(o + 4 * (size_t)ni);
     P.scan_tmp = o;           o = align_up(o + 4 * (size_t)(scan_words > part_words ? scan_words : part_words));
-    for (int b = 0; b < 2; ++b) { P.ikeys[b] = o; o = align_up(o + 8 * (size_t)ni); }
+    for (int b = 0; b < 2; ++b) { P.ikeys[b] = o; o = align_up(o + 4 * (size_t)ni); }
     for (int b = 0; b < 2; ++b) { P.ivals[b] = o; o = align_up(o + 4 * (size_t)ni); }
     for (int b = 0; b < 2; ++b) { P.ptile[b] = o; o = align_up(o + 4 * (size_t)cap); }
     for (int b = 0; b < 2; ++b) { P.pval[b] = o; o = align_up(o + 4 * (size_t)cap); }
@@ -127,7 +126,7 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.offsets = (uint32_t *)(b + P.lay.offsets);
     w.scan_tmp = (uint32_t *)(b + P.scan_tmp);
     for (int k = 0; k < 2; ++k) {
-        w.ikeys[k] = (uint64_t *)(b + P.ikeys[k]);
+        w.ikeys[k] = (uint32_t *)(b + P.ikeys[k]);
         w.ivals[k] = (uint32_t *)(b + P.ivals[k]);
         w.ptile[k] = (uint32_t *)(b + P.ptile[k]);
         w.pval[k] = (uint32_t *)(b + P.pval[k]);
@@ -146,7 +145,6 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.n = f->n;
     w.n_views = f->n_views;
     w.tile_bits = P.tile_bits;
-    w.view_bits = P.view_bits;
     w.item_blocks = P.item_blocks;
     w.pair_blocks = P.pair_blocks;
     w.pair_passes = P.pair_passes;

@@ -65,7 +65,7 @@ struct Ws {
     uint32_t *icounts;     // the same counts in depth-sorted item order
     uint32_t *offsets;     // exclusive scan of icounts
     uint32_t *scan_tmp;
-    uint64_t *ikeys[2];    // item sort keys (view << 32 | depth bits)
+    uint32_t *ikeys[2];    // item sort keys (float32 depth bits; 0xffffffff when culled)
     uint32_t *ivals[2];    // item sort values ((view, Gaussian) index)
     uint32_t *ptile[2];    // pair sort keys (global tile id)
     uint32_t *pval[2];     // pair sort values (Gaussian index)
@@ -82,7 +82,6 @@ struct Ws {
     int32_t n;
     int32_t n_views;
     int32_t tile_bits;     // bits of the largest global tile id
-    int32_t view_bits;     // bits of n_views (culled items sort after view n_views - 1)
     int32_t item_blocks;   // radix-sort blocks over the items
     int32_t pair_blocks;   // radix-sort blocks over the pair capacity
     int32_t pair_passes;   // 8-bit passes over the tile id
@@ -109,7 +108,7 @@ constexpr int kSortItems = 16;
 constexpr int kSortBlock = kSortThreads * kSortItems;   // 4096 pairs
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kMaxPasses = 5;                            // view bits + 32 depth bits, 8 at a time
+constexpr int kMaxPasses = 4;                            // 32 depth bits, 8 at a time
 constexpr int kGhStride = 32;   // words between histogram bins (spreads their atomics over channels)
 constexpr int kSortCtlWords = (kMaxPasses * kRadix + kMaxPasses) * kGhStride;
 

@@ -177,6 +177,7 @@ __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const
         const float o = g.opacity[i];
         KeyOut ko;
         uint32_t count = 0;
+        uint32_t key = 0xffffffffu;   // item sort key: depth bits, the largest when culled
         if (key_path(m, s, q, o, c, p, ko)) {
             Proj64 P;
             project64(m, s, q, c, (double)p.lowpass, P);
@@ -201,8 +202,11 @@ __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const
             count = (uint32_t)((ko.xh / T - ko.xl / T + 1) * (ko.yh / T - ko.yl / T + 1));
             dmin = dbits;
             dmax = dbits;
+            key = dbits;
         }
         ws.counts[idx] = count;
+        ws.ikeys[0][idx] = key;
+        ws.ivals[0][idx] = (uint32_t)idx;
         // clear this (view, Gaussian)'s 2-D gradient accumulator for the backward
         float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d) + 2 * idx;
         g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);

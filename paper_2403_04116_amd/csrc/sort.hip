@@ -1,15 +1,16 @@
 // Stage 2 (Sec. 3.2): the per-tile, depth-ordered Gaussian lists.
 //
 // Two stable LSD radix sorts replace one sort of (tile | depth) keys:
-//   1. items: the (view, Gaussian) records sorted by (view, depth), where
-//      the depth part is compacted on the fly to (depth bits - depth_min)
-//      over only the bits that vary among kept Gaussians, and culled items
-//      go last; equal keys keep (view, Gaussian) index order;
+//   1. items: the (view, Gaussian) records sorted by depth bits alone,
+//      compacted on the fly to (depth bits - depth_min) over only the bits
+//      that vary among kept Gaussians (culled items carry the largest key);
+//      equal keys keep (view, Gaussian) index order;
 //   2. pairs: the (tile, Gaussian) pairs, emitted in that item order, sorted
 //      by tile id only.
-// Stability makes every tile's list ordered by (depth, Gaussian index),
-// exactly the order of a sort on (tile << 32 | depth bits, index), while
-// the bulky pass over pairs moves 8-byte records on tile bits only.
+// A tile only lists Gaussians of its own view, and those appear in the
+// item order by (depth, Gaussian index); stability carries that order into
+// every tile's list, exactly the order of a sort on (tile << 32 | depth
+// bits, index), while each pass moves 8-byte records.
 //
 // Each sort is one histogram launch (the digit counts of every pass in one
 // read of the keys) and one launch per 8-bit pass, in the single-pass
@@ -31,26 +32,27 @@ namespace {
 struct Ctl {
     int64_t n;        // elements to sort
     uint32_t dmin;    // items: smallest kept depth bits
+    uint32_t dmax;    // items: largest kept depth bits
     int dbits;        // items: varying depth bits
     int total_bits;   // key bits to sort
 };
 
-// (view << 32 | depth bits) keys of the items.
+// Float32 depth bits of the items (0xffffffff for culled items, which the
+// digit clamps to the largest kept depth).
 struct ItemSort {
-    using Key = uint64_t;
+    using Key = uint32_t;
     static __device__ __forceinline__ Ctl ctl(const Ws &ws) {
         Ctl c;
         const WsHeader *h = ws.hdr;
         c.n = ws.n_items;
         c.dmin = h->depth_min;
-        const uint32_t dmax = h->depth_max;
-        c.dbits = (dmax > c.dmin) ? 32 - __clz((int)(dmax - c.dmin)) : 0;
-        c.total_bits = ws.view_bits + c.dbits;
+        c.dmax = h->depth_max;
+        c.dbits = (c.dmax > c.dmin) ? 32 - __clz((int)(c.dmax - c.dmin)) : 0;
+        c.total_bits = c.dbits;
         return c;
     }
     static __device__ __forceinline__ uint32_t digit(Key key, const Ctl &c, int shift) {
-        const uint64_t ck = ((key >> 32) << c.dbits) | (uint64_t)((uint32_t)key - c.dmin);
-        return (uint32_t)(ck >> shift) & (kRadix - 1);
+        return ((min(key, c.dmax) - c.dmin) >> shift) & (kRadix - 1);
     }
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ikeys[b]; }
     static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.ivals[b]; }
@@ -71,6 +73,7 @@ struct PairSort {
         const int64_t np = h->n_pairs;
         c.n = (h->status != XG_OK || np > ws.cap) ? 0 : np;
         c.dmin = 0;
+        c.dmax = 0;
         c.dbits = 0;
         c.total_bits = ws.tile_bits;
         return c;
@@ -334,21 +337,6 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int 
     }
 }
 
-// Item keys: (view << 32 | depth bits) for kept items, (n_views << 32 |
-// depth_min) for culled ones (they sort last); values = item index.
-__global__ __launch_bounds__(256) void k_item_keys(Ws ws) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ws.n_items) return;
-    const int v = (int)(idx / ws.n);
-    uint64_t key;
-    if (ws.counts[idx] > 0)
-        key = ((uint64_t)v << 32) | __float_as_uint(ws.rec[idx].b.w);
-    else
-        key = ((uint64_t)ws.n_views << 32) | ws.hdr->depth_min;
-    ws.ikeys[0][idx] = key;
-    ws.ivals[0][idx] = (uint32_t)idx;
-}
-
 // Tile counts in depth-sorted item order.
 __global__ __launch_bounds__(256) void k_gather_counts(Ws ws) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,9 +408,9 @@ unsigned grid256(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) 
 }  // namespace
 
 hipError_t launch_sort_items(const Ws &ws, hipStream_t s) {
-    hipLaunchKernelGGL(k_item_keys, dim3(grid256(ws.n_items)), dim3(256), 0, s, ws);
-    // worst case: view bits + 32 depth bits; passes past the varying bits return at once
-    const int passes = (ws.view_bits + 32 + kRadixBits - 1) / kRadixBits;
+    // the keys were written by the preprocess; worst case 32 varying depth
+    // bits, passes past the varying bits return at once
+    const int passes = (32 + kRadixBits - 1) / kRadixBits;
     if (passes > kMaxPasses) return hipErrorInvalidValue;
     return radix_passes<ItemSort>(ws, passes, ws.item_blocks, s);
 }
