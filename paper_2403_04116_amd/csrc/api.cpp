@@ -81,8 +81,8 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     const int64_t ni = (int64_t)f->n * f->n_views;
     const int64_t cap = f->pair_capacity;
     P.n_items = ni;
-    P.item_blocks = (int32_t)((ni + kSortBlock - 1) / kSortBlock);
-    P.pair_blocks = (int32_t)((cap + kSortBlock - 1) / kSortBlock);
+    P.item_blocks = (int32_t)((ni + kItemSortBlock - 1) / kItemSortBlock);
+    P.pair_blocks = (int32_t)((cap + kPairSortBlock - 1) / kPairSortBlock);
     P.tile_bits = bits_of(P.total_tiles - 1);
     P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
     const int64_t lb_words = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);

@@ -103,9 +103,12 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;   // 2048 elements
 
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortBlock = kSortThreads * kSortItems;   // 4096 pairs
+// Radix-sort partitions (keys per workgroup = threads x keys per thread);
+// larger partitions shorten the look-back chains, these sizes measured best.
+constexpr int kItemSortThreads = 512, kItemSortItems = 16;    // 8192 items
+constexpr int kPairSortThreads = 1024, kPairSortItems = 16;   // 16384 pairs
+constexpr int kItemSortBlock = kItemSortThreads * kItemSortItems;
+constexpr int kPairSortBlock = kPairSortThreads * kPairSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 4;                            // 32 depth bits, 8 at a time

@@ -14,7 +14,8 @@
 //
 // Each sort is one histogram launch (the digit counts of every pass in one
 // read of the keys) and one launch per 8-bit pass, in the single-pass
-// ("onesweep") form: a workgroup takes the next 4096-key partition from an
+// ("onesweep") form: a workgroup takes the next partition (8192 items or
+// 16384 pairs) from an
 // atomic counter, ranks its keys stably with wavefront ballots, publishes
 // its per-digit counts, and reads the running prefix of the partitions
 // before it from their published words (decoupled look-back: a partition
@@ -57,6 +58,7 @@ struct ItemSort {
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ikeys[b]; }
     static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.ivals[b]; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
+    static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
     static constexpr bool kSkipConstant = true;
     // the result sits in buffer (passes that moved data) & 1
     static __device__ __forceinline__ void done(const Ws &ws, int nrun) {
@@ -84,6 +86,7 @@ struct PairSort {
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ptile[b]; }
     static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.pval[b]; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
+    static constexpr int kThreads = kPairSortThreads, kItems = kPairSortItems;
     // every pass runs, so the result buffer (pair_passes & 1) is known on the host
     static constexpr bool kSkipConstant = false;
     static __device__ __forceinline__ void done(const Ws &, int) {}
@@ -103,7 +106,8 @@ constexpr int kLookback = 16;    // predecessors read per look-back step
 template <class S>
 __global__ __launch_bounds__(256) void k_sort_prep(Ws ws) {
     const Ctl c = S::ctl(ws);
-    const int64_t parts = (c.n + kSortBlock - 1) / kSortBlock;
+    constexpr int64_t kBlock = S::kThreads * S::kItems;
+    const int64_t parts = (c.n + kBlock - 1) / kBlock;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = i0; i < kSortCtlWords; i += stride) ws.ghist[i] = 0;
@@ -128,14 +132,16 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // bins.  A grid of a few workgroups per CU strides over the keys, so each
 // global bin receives few atomics.
 template <class S>
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Ws ws, int passes) {
+__global__ __launch_bounds__(S::kThreads) void k_sort_hist(Ws ws, int passes) {
     using Key = typename S::Key;
+    constexpr int kSortThreads = S::kThreads, kSortItems = S::kItems;
+    constexpr int kSortBlock = kSortThreads * kSortItems;
     constexpr int NW = kSortThreads / kWave;
     const Ctl c = S::ctl(ws);
     __shared__ uint32_t hist[NW][kMaxPasses][kRadix];
     const int w = threadIdx.x / kWave;
-    for (int q = 0; q < kMaxPasses; ++q)
-        for (int k = 0; k < NW; ++k) hist[k][q][threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < NW * kMaxPasses * kRadix; i += kSortThreads)
+        (&hist[0][0][0])[i] = 0;
     __syncthreads();
     const Key *in = S::keys(ws, 0);
     for (int64_t base = (int64_t)blockIdx.x * kSortBlock; base < c.n;
@@ -157,17 +163,20 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Ws ws, int passes) {
         }
     }
     __syncthreads();
-    for (int q = 0; q < passes; ++q) {
+    for (int i = threadIdx.x; i < passes * kRadix; i += kSortThreads) {
+        const int q = i / kRadix, d = i % kRadix;
         uint32_t h = 0;
-        for (int k = 0; k < NW; ++k) h += hist[k][q][threadIdx.x];
-        if (h) atomicAdd(&ws.ghist[(q * kRadix + threadIdx.x) * kGhStride], h);
+        for (int k = 0; k < NW; ++k) h += hist[k][q][d];
+        if (h) atomicAdd(&ws.ghist[(q * kRadix + d) * kGhStride], h);
     }
 }
 
 // One stable LSD pass on digit `pass` of `passes` launched.
 template <class S>
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int passes) {
+__global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int passes) {
     using Key = typename S::Key;
+    constexpr int kSortThreads = S::kThreads, kSortItems = S::kItems;
+    constexpr int kSortBlock = kSortThreads * kSortItems;
     const Ctl c = S::ctl(ws);
     const int shift = pass * kRadixBits;
     const int64_t parts = (c.n + kSortBlock - 1) / kSortBlock;
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int 
     {
         uint64_t *next = ws.lookback[(pass + 1) & 1];
         const int64_t slot = blockIdx.x;
-        if (slot < parts) next[slot * kRadix + threadIdx.x] = 0;
+        if (slot < parts && threadIdx.x < kRadix) next[slot * kRadix + threadIdx.x] = 0;
     }
 
     // Which passes move data: those inside the key's bits, and (items) whose
@@ -195,7 +204,9 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int 
     bool run_this = false;
     for (int q = 0; q < passes; ++q) {
         bool run = q * kRadixBits < c.total_bits && c.n > 0;
-        if (run && S::kSkipConstant) run = !__syncthreads_or(ws.ghist[(q * kRadix + threadIdx.x) * kGhStride] == (uint32_t)c.n);
+        if (run && S::kSkipConstant)
+            run = !__syncthreads_or(threadIdx.x < kRadix &&
+                                    ws.ghist[(q * kRadix + threadIdx.x) * kGhStride] == (uint32_t)c.n);
         if (run && q < pass) ++nrun_before;
         if (q == pass) run_this = run;
         if (run) ++nrun_total;
@@ -205,7 +216,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int 
     if (!run_this) return;
 
     if (threadIdx.x == 0) s_part = (int)atomicAdd(&ws.pctr[pass * kGhStride], 1u);
-    for (int k = 0; k < kSortThreads / kWave; ++k) whist[k][threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * kRadix; i += kSortThreads)
+        (&whist[0][0])[i] = 0;
     __syncthreads();
     const int64_t part = s_part;
     if (part >= parts) return;
@@ -242,70 +254,77 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(Ws ws, int pass, int 
     }
     __syncthreads();
     {
+        // threads d < 256 each own digit d
         const int d = threadIdx.x;
-        uint32_t acc = 0;
-#pragma unroll
-        for (int k = 0; k < kSortThreads / kWave; ++k) {
-            const uint32_t t = whist[k][d];
-            whist[k][d] = acc;
-            acc += t;
-        }
-        uint64_t *lb = ws.lookback[pass & 1];
-        uint64_t *mine = lb + part * kRadix + d;
-        // publish this partition's count, then add up the predecessors'
-        if (part == 0) {
-            __hip_atomic_store(mine, kLbPrefix | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(mine, kLbAggregate | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // Look back over a window of kLookback predecessors at a time (their
-        // words are loaded together): add aggregates until a prefix; a
-        // predecessor that has not published yet is polled again.
-        uint32_t excl = 0;
+        const bool dig = d < kRadix;
+        uint32_t acc = 0, excl = 0;
         bool failed = false;
-        uint32_t spins = 0;
-        for (int64_t q = part - 1; q >= 0;) {
-            uint64_t word[kLookback];
+        if (dig) {
 #pragma unroll
-            for (int k = 0; k < kLookback; ++k)
-                word[k] = (q - k >= 0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : kLbPrefix;     // before partition 0: prefix 0
-            int used = 0;
-            bool stop = false, wait = false;
+            for (int k = 0; k < kSortThreads / kWave; ++k) {
+                const uint32_t t = whist[k][d];
+                whist[k][d] = acc;
+                acc += t;
+            }
+            uint64_t *lb = ws.lookback[pass & 1];
+            uint64_t *mine = lb + part * kRadix + d;
+            // publish this partition's count, then add up the predecessors'
+            if (part == 0) {
+                __hip_atomic_store(mine, kLbPrefix | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(mine, kLbAggregate | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // Look back over a window of kLookback predecessors at a time (their
+            // words are loaded together): add aggregates until a prefix; a
+            // predecessor that has not published yet is polled again.
+            uint32_t spins = 0;
+            for (int64_t q = part - 1; q >= 0;) {
+                uint64_t word[kLookback];
 #pragma unroll
-            for (int k = 0; k < kLookback; ++k) {
-                if (stop || wait) continue;
-                const uint64_t flag = word[k] & (3ull << 62);
-                if (flag == 0) {
-                    wait = true;
-                } else {
-                    excl += (uint32_t)word[k];
-                    ++used;
-                    stop = flag == kLbPrefix;
+                for (int k = 0; k < kLookback; ++k)
+                    word[k] = (q - k >= 0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT)
+                                           : kLbPrefix;     // before partition 0: prefix 0
+                int used = 0;
+                bool stop = false, wait = false;
+#pragma unroll
+                for (int k = 0; k < kLookback; ++k) {
+                    if (stop || wait) continue;
+                    const uint64_t flag = word[k] & (3ull << 62);
+                    if (flag == 0) {
+                        wait = true;
+                    } else {
+                        excl += (uint32_t)word[k];
+                        ++used;
+                        stop = flag == kLbPrefix;
+                    }
+                }
+                if (stop) break;
+                q -= used;
+                if (wait) {
+                    if (++spins > kSpinLimit) {
+                        failed = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
             }
-            if (stop) break;
-            q -= used;
-            if (wait) {
-                if (++spins > kSpinLimit) {
-                    failed = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+            if (part != 0)
+                __hip_atomic_store(mine, kLbPrefix | (uint32_t)(excl + acc), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (failed) __hip_atomic_store(&ws.hdr->status, (int32_t)XG_EHIP, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (part != 0)
-            __hip_atomic_store(mine, kLbPrefix | (uint32_t)(excl + acc), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        if (failed) __hip_atomic_store(&ws.hdr->status, (int32_t)XG_EHIP, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
         // global start of digit d: keys with smaller digits, then this digit's
         // keys in earlier partitions
         uint32_t tot;
-        const uint32_t dstart = block_excl_scan(ws.ghist[(pass * kRadix + d) * kGhStride], scan_lds, &tot);
-        goff[d] = dstart + excl;
-        bstart[d] = block_excl_scan(acc, scan_lds, &tot);
+        const uint32_t dstart = block_excl_scan(dig ? ws.ghist[(pass * kRadix + d) * kGhStride] : 0u,
+                                                scan_lds, &tot);
+        const uint32_t bs = block_excl_scan(acc, scan_lds, &tot);
+        if (dig) {
+            goff[d] = dstart + excl;
+            bstart[d] = bs;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -397,9 +416,9 @@ hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s) {
     if (np > 2048) np = 2048;
     hipLaunchKernelGGL(k_sort_prep<S>, dim3(np > 0 ? np : 1), dim3(256), 0, s, ws);
     const unsigned nh = nb < 512 ? nb : 512;
-    hipLaunchKernelGGL(k_sort_hist<S>, dim3(nh), dim3(kSortThreads), 0, s, ws, passes);
+    hipLaunchKernelGGL(k_sort_hist<S>, dim3(nh), dim3(S::kThreads), 0, s, ws, passes);
     for (int p = 0; p < passes; ++p)
-        hipLaunchKernelGGL(k_onesweep<S>, dim3(nb), dim3(kSortThreads), 0, s, ws, p, passes);
+        hipLaunchKernelGGL(k_onesweep<S>, dim3(nb), dim3(S::kThreads), 0, s, ws, p, passes);
     return hipGetLastError();
 }
 
