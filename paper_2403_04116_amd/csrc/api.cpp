@@ -279,9 +279,7 @@ xg_status xg_preprocess(const xg_frame *f, const xg_gaussians *g, void *stream) 
     hipStream_t s = (hipStream_t)stream;
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
-    hipError_t e = launch_reset(ws, s);
-    if (e == hipSuccess && ws.n_items > 0) e = launch_preprocess(ws, *g, f->cams_dev, p, s);
-    return hip_status(e);
+    return hip_status(launch_preprocess(ws, *g, f->cams_dev, p, s));
 }
 
 xg_status xg_bin_sort(const xg_frame *f, void *stream) {
@@ -294,14 +292,13 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
     hipError_t e = hipSuccess;
     if (ws.n_items > 0) {
         e = launch_sort_items(ws, s);
-        if (e == hipSuccess) e = launch_gather_counts(ws, s);
         if (e == hipSuccess)
             e = launch_scan(ws.icounts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
                             &ws.hdr->status, ws.cap, s);
         if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
         if (e == hipSuccess) e = launch_sort_pairs(ws, s);
     }
-    if (e == hipSuccess) e = launch_ranges(ws, s);
+    if (e == hipSuccess) e = launch_ranges(ws, ws.n_items > 0, s);
     return hip_status(e);
 }
 

@@ -22,7 +22,8 @@ struct WsHeader {
     int32_t queue_bwd;     // persistent backward tile queue head
     int32_t done_fwd;      // persistent forward workgroups finished
     int32_t done_bwd;      // persistent backward workgroups finished
-    int32_t pad[55];
+    int32_t item_passes;   // item-sort passes that moved data
+    int32_t pad[54];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
 
@@ -116,16 +117,14 @@ constexpr int kGhStride = 32;   // words between histogram bins (spreads their a
 constexpr int kSortCtlWords = (kMaxPasses * kRadix + kMaxPasses) * kGhStride;
 
 // ---- launchers (one translation unit per stage) --------------------------
-hipError_t launch_reset(const Ws &ws, hipStream_t s);
 hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                              const Params &p, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
                        int32_t *total, int32_t *status, int64_t cap, hipStream_t s);
 hipError_t launch_sort_items(const Ws &ws, hipStream_t s);
-hipError_t launch_gather_counts(const Ws &ws, hipStream_t s);
 hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s);
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s);
-hipError_t launch_ranges(const Ws &ws, hipStream_t s);
+hipError_t launch_ranges(const Ws &ws, bool cleared, hipStream_t s);  // cleared: by the pair sort
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
 // Per-pixel stored transmittances of the stored-list variant: count[tile][px]
 // contributors, then t[tile][slot][px] = T before contributor `slot` (the

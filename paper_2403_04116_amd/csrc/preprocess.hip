@@ -110,6 +110,7 @@ __device__ __forceinline__ void quat_rot(const double q[4], double R[9]) {
 struct Proj64 {
     double t[3];
     double qn;          // norm of the input quaternion
+    double rtz;         // 1 / t_z
     double q[4];        // unit quaternion
     double R[9];
     double J[6];        // first two rows of J (Eq. 9)
@@ -127,12 +128,16 @@ __device__ __forceinline__ void project64(const float *m, const float *s, const 
     for (int a = 0; a < 3; ++a)
         P.t[a] = r[3 * a] * m[0] + r[3 * a + 1] * m[1] + r[3 * a + 2] * m[2] + (double)c.trans[a];
     double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    // one float64 reciprocal per divisor (the float32 results these feed
+    // are rounded once; the extra float64 rounding is far below that)
     P.qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    P.q[0] = q0 / P.qn; P.q[1] = q1 / P.qn; P.q[2] = q2 / P.qn; P.q[3] = q3 / P.qn;
+    const double rqn = 1.0 / P.qn;
+    P.q[0] = q0 * rqn; P.q[1] = q1 * rqn; P.q[2] = q2 * rqn; P.q[3] = q3 * rqn;
     quat_rot(P.q, P.R);
     double fx = c.fx, fy = c.fy, tz = P.t[2];
-    P.J[0] = fx / tz; P.J[1] = 0.0; P.J[2] = -fx * P.t[0] / (tz * tz);
-    P.J[3] = 0.0; P.J[4] = fy / tz; P.J[5] = -fy * P.t[1] / (tz * tz);
+    P.rtz = 1.0 / tz;
+    P.J[0] = fx * P.rtz; P.J[1] = 0.0; P.J[2] = -fx * P.t[0] * (P.rtz * P.rtz);
+    P.J[3] = 0.0; P.J[4] = fy * P.rtz; P.J[5] = -fy * P.t[1] * (P.rtz * P.rtz);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -149,19 +154,6 @@ __device__ __forceinline__ void project64(const float *m, const float *s, const 
     P.sxy = P.B[0] * P.B[3] + P.B[1] * P.B[4] + P.B[2] * P.B[5];
 }
 
-__global__ void k_reset(WsHeader *h) {
-    if (threadIdx.x == 0) {
-        h->status = XG_OK;
-        h->n_pairs = 0;
-        h->item_sel = 0;
-        h->depth_min = 0xffffffffu;
-        h->depth_max = 0u;
-        h->queue_fwd = 0;
-        h->queue_bwd = 0;
-        h->done_fwd = 0;
-        h->done_bwd = 0;
-    }
-}
 
 __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const xg_camera *cams,
                                                     Params p, uint32_t *depth_part) {
@@ -184,11 +176,12 @@ __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const
             double det = P.sxx * P.syy - P.sxy * P.sxy;
             const double k = (double)kLog2eHalf;
             // k d^T Sigma''^-1 d = (qa dx + qb dy)^2 + (qc dy)^2
-            double qa = sqrt(k * P.syy / det);
-            double qb = -k * P.sxy / (det * qa);
+            const double rdet = 1.0 / det;
+            double qa = sqrt(k * P.syy * rdet);
+            double qb = -k * P.sxy * rdet / qa;
             double qc = sqrt(k / P.syy);
-            double ux = (double)c.fx * P.t[0] / P.t[2] + (double)c.cx;
-            double uy = (double)c.fy * P.t[1] / P.t[2] + (double)c.cy;
+            double ux = (double)c.fx * P.t[0] * P.rtz + (double)c.cx;
+            double uy = (double)c.fy * P.t[1] * P.rtz + (double)c.cy;
             double fx_ = floor(ux), fy_ = floor(uy);
             fx_ = fmin(fmax(fx_, -1073741824.0), 1073741824.0);
             fy_ = fmin(fmax(fy_, -1073741824.0), 1073741824.0);
@@ -231,7 +224,8 @@ __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const
     }
 }
 
-// Reduces the per-block depth partials into the header (one block).
+// Resets the header for a new frame and reduces the per-block depth
+// partials into it (one block; nparts may be 0).
 __global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_t *part, int nparts) {
     uint32_t dmin = 0xffffffffu, dmax = 0u;
     for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
@@ -253,6 +247,14 @@ __global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_
         }
         h->depth_min = dmin;
         h->depth_max = dmax;
+        h->status = XG_OK;
+        h->n_pairs = 0;
+        h->item_sel = 0;
+        h->item_passes = 0;
+        h->queue_fwd = 0;
+        h->queue_bwd = 0;
+        h->done_fwd = 0;
+        h->done_bwd = 0;
     }
 }
 
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_
 // The pairs of a workgroup's 256 consecutive items form one contiguous
 // range; when it fits, they are assembled in LDS and written as whole
 // lines, else each item writes its own.
-constexpr int kEmitStage = 4096;
+constexpr int kEmitStage = 2048;   // 16 KB of LDS: eight workgroups per CU
 
 __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int tile) {
     __shared__ uint32_t s_t[kEmitStage];
@@ -364,7 +366,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
 #pragma unroll
         for (int k = 0; k < 9; ++k) r[k] = (double)c.rot[k];
         const double det = P.sxx * P.syy - P.sxy * P.sxy;
-        const double QA = P.syy / det, QB = -P.sxy / det, QC = P.sxx / det;
+        const double rdet = 1.0 / det;
+        const double QA = P.syy * rdet, QB = -P.sxy * rdet, QC = P.sxx * rdet;
         const double gux = QA * (double)g0.x + QB * (double)g0.y;
         const double guy = QB * (double)g0.x + QC * (double)g0.y;
         // dL/dSigma'' = -Q G_Q Q, off-diagonal of G_Q carrying half of dL/dB
@@ -415,22 +418,23 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         double gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4]
                          + y * GR[5] + x * GR[6] + y * GR[7]);
         const double dot = w * gw + x * gx + y * gy + z * gz;
-        gq[0] += (gw - w * dot) / P.qn;
-        gq[1] += (gx - x * dot) / P.qn;
-        gq[2] += (gy - y * dot) / P.qn;
-        gq[3] += (gz - z * dot) / P.qn;
+        const double rqn = 1.0 / P.qn;
+        gq[0] += (gw - w * dot) * rqn;
+        gq[1] += (gx - x * dot) * rqn;
+        gq[2] += (gy - y * dot) * rqn;
+        gq[3] += (gz - z * dot) * rqn;
         // A2 = J W: dL/dJ = GA2 W^T (only the non-zero entries of J)
         const double GJ00 = GA2[0] * r[0] + GA2[1] * r[1] + GA2[2] * r[2];
         const double GJ02 = GA2[0] * r[6] + GA2[1] * r[7] + GA2[2] * r[8];
         const double GJ11 = GA2[3] * r[3] + GA2[4] * r[4] + GA2[5] * r[5];
         const double GJ12 = GA2[3] * r[6] + GA2[4] * r[7] + GA2[5] * r[8];
-        const double fx = c.fx, fy = c.fy, tx = P.t[0], ty = P.t[1], tz = P.t[2];
-        const double tz2 = tz * tz, tz3 = tz2 * tz;
-        const double gtx = GJ02 * (-fx / tz2) + gux * (fx / tz);
-        const double gty = GJ12 * (-fy / tz2) + guy * (fy / tz);
-        const double gtz = GJ00 * (-fx / tz2) + GJ02 * (2.0 * fx * tx / tz3)
-                           + GJ11 * (-fy / tz2) + GJ12 * (2.0 * fy * ty / tz3)
-                           + gux * (-fx * tx / tz2) + guy * (-fy * ty / tz2);
+        const double fx = c.fx, fy = c.fy, tx = P.t[0], ty = P.t[1];
+        const double r1 = P.rtz, r2 = r1 * r1, r3 = r2 * r1;
+        const double gtx = GJ02 * (-fx * r2) + gux * (fx * r1);
+        const double gty = GJ12 * (-fy * r2) + guy * (fy * r1);
+        const double gtz = GJ00 * (-fx * r2) + GJ02 * (2.0 * fx * tx * r3)
+                           + GJ11 * (-fy * r2) + GJ12 * (2.0 * fy * ty * r3)
+                           + gux * (-fx * tx * r2) + guy * (-fy * ty * r2);
         // t = W mu + tau
 #pragma unroll
         for (int a = 0; a < 3; ++a) gm[a] += r[a] * gtx + r[3 + a] * gty + r[6 + a] * gtz;
@@ -484,10 +488,6 @@ int grid_for(int64_t n, int threads, int max_blocks = 65536) {
 
 }  // namespace
 
-hipError_t launch_reset(const Ws &ws, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws.hdr);
-    return hipGetLastError();
-}
 
 hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                              const Params &p, hipStream_t s) {
@@ -496,9 +496,9 @@ hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camer
     // depth partials live in the scan scratch; the count scan runs after
     // k_depth_range has consumed them
     uint32_t *part = ws.scan_tmp;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws, g, cams,
-                       p, part);
-    hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1024), 0, s, ws.hdr, part, (int)(nb > 0 ? nb : 1));
+    if (nb > 0)
+        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)nb), dim3(256), 0, s, ws, g, cams, p, part);
+    hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1024), 0, s, ws.hdr, part, (int)nb);
     return hipGetLastError();
 }
 

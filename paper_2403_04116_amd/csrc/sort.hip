@@ -60,9 +60,13 @@ struct ItemSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
     static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
     static constexpr bool kSkipConstant = true;
+    // the last pass that moves data also writes the tile counts in sorted order
+    static constexpr bool kGatherCounts = true;
+    static constexpr bool kClearRanges = false;
     // the result sits in buffer (passes that moved data) & 1
     static __device__ __forceinline__ void done(const Ws &ws, int nrun) {
         ws.hdr->item_sel = nrun & 1;
+        ws.hdr->item_passes = nrun;
     }
 };
 
@@ -87,6 +91,9 @@ struct PairSort {
     static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.pval[b]; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPairSortThreads, kItems = kPairSortItems;
+    static constexpr bool kGatherCounts = false;
+    // the tile ranges are cleared here, ahead of k_ranges
+    static constexpr bool kClearRanges = true;
     // every pass runs, so the result buffer (pair_passes & 1) is known on the host
     static constexpr bool kSkipConstant = false;
     static __device__ __forceinline__ void done(const Ws &, int) {}
@@ -112,6 +119,8 @@ __global__ __launch_bounds__(256) void k_sort_prep(Ws ws) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = i0; i < kSortCtlWords; i += stride) ws.ghist[i] = 0;
     for (int64_t i = i0; i < parts * kRadix; i += stride) ws.lookback[0][i] = 0;
+    if (S::kClearRanges)
+        for (int64_t i = i0; i < 2 * ws.total_tiles; i += stride) ws.ranges[i] = 0;
 }
 
 // Lanes of the wavefront whose digit equals this lane's (one ballot per
@@ -211,7 +220,14 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
         if (q == pass) run_this = run;
         if (run) ++nrun_total;
     }
+    // the item sort always moves its data at least once (its last pass writes
+    // the tile counts in sorted order), even when every key is equal
+    if (S::kGatherCounts && nrun_total == 0 && c.n > 0) {
+        nrun_total = 1;
+        run_this = pass == 0;
+    }
     const int in_sel = S::kSkipConstant ? (nrun_before & 1) : (pass & 1);
+    const bool last_run = nrun_before + 1 == nrun_total;
     if (pass == passes - 1 && blockIdx.x == 0 && threadIdx.x == 0) S::done(ws, nrun_total);
     if (!run_this) return;
 
@@ -351,16 +367,10 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
             if (dst < (uint64_t)c.n) {   // always true unless a look-back gave up
                 kout[dst] = kk;
                 vout[dst] = svals[pos];
+                if (S::kGatherCounts && last_run) ws.icounts[dst] = ws.counts[svals[pos]];
             }
         }
     }
-}
-
-// Tile counts in depth-sorted item order.
-__global__ __launch_bounds__(256) void k_gather_counts(Ws ws) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ws.n_items) return;
-    ws.icounts[j] = ws.counts[ws.ivals[ws.hdr->item_sel & 1][j]];
 }
 
 // ranges[2g], ranges[2g+1] = [start, end) of tile g in the sorted pairs
@@ -434,10 +444,6 @@ hipError_t launch_sort_items(const Ws &ws, hipStream_t s) {
     return radix_passes<ItemSort>(ws, passes, ws.item_blocks, s);
 }
 
-hipError_t launch_gather_counts(const Ws &ws, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_counts, dim3(grid256(ws.n_items)), dim3(256), 0, s, ws);
-    return hipGetLastError();
-}
 
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s) {
     if (ws.pair_passes > kMaxPasses) return hipErrorInvalidValue;
@@ -449,9 +455,11 @@ hipError_t launch_tile_order(const Ws &ws, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const Ws &ws, hipStream_t s) {
-    hipError_t e = launch_fill_u32(ws.ranges, 0u, 2 * ws.total_tiles, s);
-    if (e != hipSuccess) return e;
+hipError_t launch_ranges(const Ws &ws, bool cleared, hipStream_t s) {
+    if (!cleared) {
+        const hipError_t e = launch_fill_u32(ws.ranges, 0u, 2 * ws.total_tiles, s);
+        if (e != hipSuccess) return e;
+    }
     int64_t nb = (ws.cap + 255) / 256;
     if (nb > 16384) nb = 16384;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws);
