@@ -35,6 +35,7 @@ FLOPS_EVAL = 14          # one alpha evaluation at a pixel (offset, exponent, ex
 FLOPS_BLEND = 6          # blending a contributor (transmittance update, test, accumulate)
 FLOPS_ADJOINT = 28       # adjoint of one contributor (transmittance recovery, 7 gradients)
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
+PEAK_HBM_BPS = 8.0e12     # MI355X HBM3E
 
 
 def parse():
@@ -125,15 +126,26 @@ def main():
     gr = P.XgGrads(*(grads[k].data_ptr() for k in P.drr.PARAMS))
     sid = int(stream.cuda_stream)
     image, final_t, n_contrib = out
-    ev = {k: [] for k in ("fwd0", "fwd1", "bwd0", "bwd1")}
+    # per-stage HIP events on the launch stream: marks[k] follows stage k
+    STAGES = ["zero_grads", "preprocess", "bin_sort", "render_fwd", "l1_grad", "render_bwd",
+              "preprocess_bwd"] + (["adam"] if opt is not None else [])
+    marks = []
+
+    def mark(record, row):
+        if record:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            row.append(e)
 
     def step_batched(record: bool):
+        row = []
+        mark(record, row)
         grads.zero_()
+        mark(record, row)
         P.xg_preprocess(frame.frame, gs, sid)
+        mark(record, row)
         P.xg_bin_sort(frame.frame, sid)
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+        mark(record, row)
         if store is None:
             P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
                             n_contrib.data_ptr(), sid)
@@ -141,27 +153,23 @@ def main():
             X.xg_render_fwd_store(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
                                   n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
                                   store.view.numel(), sid)
-        if record:
-            e1 = torch.cuda.Event(enable_timing=True)
-            e1.record(stream)
+        mark(record, row)
         P.xg_l1_grad(image.data_ptr(), target.data_ptr(), dl.data_ptr(), npx, scale, sid)
-        if record:
-            e2 = torch.cuda.Event(enable_timing=True)
-            e2.record(stream)
+        mark(record, row)
         if store is None:
             P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
         else:
             X.xg_render_bwd_store(frame.frame, dl.data_ptr(), final_t.data_ptr(),
                                   n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
                                   store.view.numel(), sid)
-        if record:
-            e3 = torch.cuda.Event(enable_timing=True)
-            e3.record(stream)
-            ev["fwd0"].append(e0); ev["fwd1"].append(e1)
-            ev["bwd0"].append(e2); ev["bwd1"].append(e3)
+        mark(record, row)
         P.xg_preprocess_bwd(frame.frame, gs, gr, sid)
+        mark(record, row)
         if opt is not None:
             opt.step(grads, sid, gate=frame.status_ptr())
+            mark(record, row)
+        if record:
+            marks.append(row)
 
     def timed(fn, steps, warmup, **kw):
         for _ in range(warmup):
@@ -185,8 +193,9 @@ def main():
            "store": int(store.view.numel()) if store is not None else 0,
            "optimizer_state": int(opt.m.numel() * 8 + sum(t.numel() * 4 for t in opt.raw.values()))
            if opt is not None else 0}
-    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev["fwd0"], ev["fwd1"])]))
-    bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev["bwd0"], ev["bwd1"])]))
+    stage_ms = {name: float(np.mean([row[k].elapsed_time(row[k + 1]) for row in marks]))
+                for k, name in enumerate(STAGES)}
+    fwd_ms, bwd_ms = stage_ms["render_fwd"], stage_ms["render_bwd"]
 
     counts = frame.render_counts().double().sum(dim=1).cpu().numpy()
     evals, contribs, upto = (float(x) for x in counts)
@@ -197,6 +206,33 @@ def main():
     else:
         dom, dom_ms, dom_flops = "k_render_fwd", fwd_ms, fwd_flops
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+
+    # per-stage algorithmic work and fraction of the stage's roofline
+    n_items = w.n * w.n_views
+    n_kept = int((frame.ws_tensor(frame.layout.counts, torch.int32, n_items) > 0).sum())
+    # header word 9 of the workspace: item-sort passes that moved data
+    item_passes = int(frame.ws[36:40].view(torch.int32).item())
+    npairs = frame.n_pairs()
+    pair_passes = (max(frame.total_tiles - 1, 1).bit_length() + 7) // 8
+    work = {
+        "zero_grads": ("hbm", 48 * w.n),
+        "preprocess": ("hbm", 48 * w.n + (64 + 4 + 8 + 32) * n_items),
+        "bin_sort": ("hbm", n_items * (4 + 16 * item_passes + 8 + 12) + 16 * n_kept
+                     + npairs * (8 + 4 + 16 * pair_passes + 4) + 8 * frame.total_tiles),
+        "render_fwd": ("alu", fwd_flops),
+        "l1_grad": ("hbm", 12 * npx),
+        "render_bwd": ("alu", bwd_flops),
+        "preprocess_bwd": ("hbm", 32 * n_items + 144 * w.n),
+        "adam": ("hbm", 12 * w.n * 30),
+    }
+    stages = {}
+    for name in STAGES:
+        bound, wk = work[name]
+        ms = stage_ms[name]
+        rate = wk / (ms * 1e-3)
+        stages[name] = {"ms": ms, "bound": bound, "work": wk,
+                        "unit": "bytes" if bound == "hbm" else "flop",
+                        "frac": rate / (PEAK_HBM_BPS if bound == "hbm" else PEAK_FP32_TFLOPS * 1e12)}
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
@@ -324,6 +360,7 @@ def main():
         "per_view": per_view,
         "batched_over_per_view": (value / per_view["value"]) if per_view else None,
         "kernels_ms": {"k_render_fwd": fwd_ms, "k_render_bwd": bwd_ms},
+        "stages": stages,
         "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
                  "revisited": upto},
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),

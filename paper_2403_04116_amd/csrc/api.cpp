@@ -87,7 +87,8 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
     const int64_t lb_words = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);
     const int64_t scan_words = (ni + kScanBlock - 1) / kScanBlock + 1;
-    const int64_t part_words = 2 * ((ni + 255) / 256) + 2;
+    // depth partials: one pair per preprocess workgroup
+    const int64_t part_words = 2 * ((ni + kPreThreads - 1) / kPreThreads) + 2;
     size_t o = 0;
     xg_ws_layout &L = P.lay;
     memset(&L, 0, sizeof(L));

@@ -100,6 +100,9 @@ struct Params {
 constexpr float kLog2eHalf = 0.72134752044448170368f;   // log2(e) / 2
 constexpr float kInvLog2eHalf = 1.38629436111989061883f; // 2 ln 2
 
+// Preprocess workgroups: 256 threads, one per (view, Gaussian).
+constexpr int kPreThreads = 256;
+
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;   // 2048 elements

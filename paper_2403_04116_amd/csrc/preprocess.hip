@@ -20,18 +20,13 @@ namespace {
 struct KeyOut {
     float tz;
     int xl, xh, yl, yh;
+    int ok;
 };
 
-__device__ __noinline__ bool key_path(const float *m, const float *s, const float *q, float o,
-                                      const xg_camera &c, const Params &p, KeyOut &out) {
+// The unit quaternion, R and M = R diag(s); false when the quaternion is
+// zero (the Gaussian is culled in every view).
+__device__ __forceinline__ bool key_gaussian(const float *s, const float *q, float *M) {
 #pragma clang fp contract(off)
-    const float *r = c.rot;
-    float mx = m[0], my = m[1], mz = m[2];
-    float tx = ((r[0] * mx + r[1] * my) + r[2] * mz) + c.trans[0];
-    float ty = ((r[3] * mx + r[4] * my) + r[5] * mz) + c.trans[1];
-    float tz = ((r[6] * mx + r[7] * my) + r[8] * mz) + c.trans[2];
-    if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) return false;
-    if (!(tz > p.near_z)) return false;
     float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
     float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     if (!(n2 > 0.0f)) return false;
@@ -47,13 +42,26 @@ __device__ __noinline__ bool key_path(const float *m, const float *s, const floa
     R[6] = 2.0f * (x * z - w * y);
     R[7] = 2.0f * (y * z + w * x);
     R[8] = 1.0f - 2.0f * (x * x + y * y);
-    float M[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         M[3 * a + 0] = R[3 * a + 0] * s[0];
         M[3 * a + 1] = R[3 * a + 1] * s[1];
         M[3 * a + 2] = R[3 * a + 2] * s[2];
     }
+    return true;
+}
+
+// Camera-space centre, culling, Sigma'', rectangle in one view.
+__device__ __forceinline__ bool key_view(const float *m, const float *M, float o,
+                                         const xg_camera &c, const Params &p, KeyOut &out) {
+#pragma clang fp contract(off)
+    const float *r = c.rot;
+    float mx = m[0], my = m[1], mz = m[2];
+    float tx = ((r[0] * mx + r[1] * my) + r[2] * mz) + c.trans[0];
+    float ty = ((r[3] * mx + r[4] * my) + r[5] * mz) + c.trans[1];
+    float tz = ((r[6] * mx + r[7] * my) + r[8] * mz) + c.trans[2];
+    if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) return false;
+    if (!(tz > p.near_z)) return false;
     float tz2 = tz * tz;
     float J00 = c.fx / tz;
     float J11 = c.fy / tz;
@@ -105,21 +113,35 @@ __device__ __forceinline__ void quat_rot(const double q[4], double R[9]) {
     R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
 }
 
-// Float64 projection of one Gaussian: camera-space centre t, the 2x3
-// matrix B = J W R diag(s) with Sigma'' = B B^T + k I, and Sigma''.
-struct Proj64 {
-    double t[3];
+// Float64 per-Gaussian part: the unit quaternion and its rotation matrix.
+struct Gauss64 {
     double qn;          // norm of the input quaternion
-    double rtz;         // 1 / t_z
     double q[4];        // unit quaternion
     double R[9];
+};
+
+__device__ __forceinline__ void gauss64(const float *q, Gauss64 &G) {
+    double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    G.qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    // one float64 reciprocal per divisor (the float32 results these feed
+    // are rounded once; the extra float64 rounding is far below that)
+    const double rqn = 1.0 / G.qn;
+    G.q[0] = q0 * rqn; G.q[1] = q1 * rqn; G.q[2] = q2 * rqn; G.q[3] = q3 * rqn;
+    quat_rot(G.q, G.R);
+}
+
+// Float64 projection of one Gaussian into one view: camera-space centre t,
+// the 2x3 matrix B = J W R diag(s) with Sigma'' = B B^T + k I, and Sigma''.
+struct Proj64 {
+    double t[3];
+    double rtz;         // 1 / t_z
     double J[6];        // first two rows of J (Eq. 9)
     double A2[6];       // J W
     double B[6];        // J W R diag(s)
     double sxx, sxy, syy;
 };
 
-__device__ __forceinline__ void project64(const float *m, const float *s, const float *q,
+__device__ __forceinline__ void project64(const float *m, const float *s, const double *R,
                                           const xg_camera &c, double lowpass, Proj64 &P) {
     double r[9];
 #pragma unroll
@@ -127,13 +149,6 @@ __device__ __forceinline__ void project64(const float *m, const float *s, const 
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         P.t[a] = r[3 * a] * m[0] + r[3 * a + 1] * m[1] + r[3 * a + 2] * m[2] + (double)c.trans[a];
-    double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
-    // one float64 reciprocal per divisor (the float32 results these feed
-    // are rounded once; the extra float64 rounding is far below that)
-    P.qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    const double rqn = 1.0 / P.qn;
-    P.q[0] = q0 * rqn; P.q[1] = q1 * rqn; P.q[2] = q2 * rqn; P.q[3] = q3 * rqn;
-    quat_rot(P.q, P.R);
     double fx = c.fx, fy = c.fy, tz = P.t[2];
     P.rtz = 1.0 / tz;
     P.J[0] = fx * P.rtz; P.J[1] = 0.0; P.J[2] = -fx * P.t[0] * (P.rtz * P.rtz);
@@ -147,32 +162,51 @@ __device__ __forceinline__ void project64(const float *m, const float *s, const 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            P.B[3 * i + k] = (P.A2[3 * i] * P.R[k] + P.A2[3 * i + 1] * P.R[3 + k]
-                              + P.A2[3 * i + 2] * P.R[6 + k]) * (double)s[k];
+            P.B[3 * i + k] = (P.A2[3 * i] * R[k] + P.A2[3 * i + 1] * R[3 + k]
+                              + P.A2[3 * i + 2] * R[6 + k]) * (double)s[k];
     P.sxx = P.B[0] * P.B[0] + P.B[1] * P.B[1] + P.B[2] * P.B[2] + lowpass;
     P.syy = P.B[3] * P.B[3] + P.B[4] * P.B[4] + P.B[5] * P.B[5] + lowpass;
     P.sxy = P.B[0] * P.B[3] + P.B[1] * P.B[4] + P.B[2] * P.B[5];
 }
 
+// The key path of one (view, Gaussian), kept out of line so its operation
+// sequence is compiled on its own.
+// (Returned by value: an out-parameter of an out-of-line call lives in
+// scratch memory.)
+__device__ __noinline__ KeyOut key_path(const float *m, const float *s, const float *q, float o,
+                                        const xg_camera &c, const Params p) {
+    float M[9];
+    KeyOut out;
+    out.ok = key_gaussian(s, q, M) && key_view(m, M, o, c, p, out);
+    return out;
+}
 
-__global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const xg_camera *cams,
-                                                    Params p, uint32_t *depth_part) {
+// One thread per (view, Gaussian), view-major, so each view's records are
+// written contiguously.  (Sharing the per-Gaussian part of the projection
+// across a workgroup's views through LDS measured slower: the lower
+// occupancy and the serial per-Gaussian phase cost more than the work it
+// saves.)
+__global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians g,
+                                                            const xg_camera *cams, Params p,
+                                                            uint32_t *depth_part) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t dmin = 0xffffffffu, dmax = 0u;
     if (idx < ws.n_items) {
         const int v = (int)(idx / ws.n);
-        const int i = (int)(idx - (int64_t)v * ws.n);
+        const int64_t i = idx - (int64_t)v * ws.n;
         const xg_camera &c = cams[v];
-        const float *m = g.means + 3 * (int64_t)i;
-        const float *s = g.scales + 3 * (int64_t)i;
-        const float *q = g.quats + 4 * (int64_t)i;
+        const float *m = g.means + 3 * i;
+        const float *s = g.scales + 3 * i;
+        const float *q = g.quats + 4 * i;
         const float o = g.opacity[i];
-        KeyOut ko;
         uint32_t count = 0;
         uint32_t key = 0xffffffffu;   // item sort key: depth bits, the largest when culled
-        if (key_path(m, s, q, o, c, p, ko)) {
+        const KeyOut ko = key_path(m, s, q, o, c, p);
+        if (ko.ok) {
+            Gauss64 G64;
+            gauss64(q, G64);
             Proj64 P;
-            project64(m, s, q, c, (double)p.lowpass, P);
+            project64(m, s, G64.R, c, (double)p.lowpass, P);
             double det = P.sxx * P.syy - P.sxy * P.sxy;
             const double k = (double)kLog2eHalf;
             // k d^T Sigma''^-1 d = (qa dx + qb dy)^2 + (qc dy)^2
@@ -210,12 +244,12 @@ __global__ __launch_bounds__(256) void k_preprocess(Ws ws, xg_gaussians g, const
         dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, kWave));
         dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, kWave));
     }
-    __shared__ uint32_t smin[4], smax[4];
+    __shared__ uint32_t smin[kPreThreads / kWave], smax[kPreThreads / kWave];
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) { smin[w] = dmin; smax[w] = dmax; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) {
+        for (int k = 1; k < kPreThreads / kWave; ++k) {
             dmin = min(dmin, smin[k]);
             dmax = max(dmax, smax[k]);
         }
@@ -336,22 +370,19 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
 // With power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 and [[A, B], [B, C]] the
 // inverse 2-D covariance: dL/du = [[A, B], [B, C]] (sum g d),
 // dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy, dL/dC = -sum g dy^2 / 2.
-//
-// L lanes share one Gaussian (views sub, sub + L, ...) and sum their
-// partial gradients with lane shuffles, so a launch has n * L threads.
-template <int L>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
                                                         Params p, xg_grads gr) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t / L);
-    const int sub = (int)(t % L);
-    if (i >= ws.n) return;     // whole groups of L lanes leave together
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ws.n) return;
     const float *m = g.means + 3 * (int64_t)i;
     const float *s = g.scales + 3 * (int64_t)i;
     const float *q = g.quats + 4 * (int64_t)i;
     double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0, gi = 0;
     bool any = false;
-    for (int v = sub; v < ws.n_views; v += L) {
+    Gauss64 G;
+    gauss64(q, G);
+    const double rqn = 1.0 / G.qn;
+    for (int v = 0; v < ws.n_views; ++v) {
         const int64_t idx = (int64_t)v * ws.n + i;
         if (ws.counts[idx] == 0) continue;
         const float4 g0 = reinterpret_cast<const float4 *>(ws.grad2d)[2 * idx];
@@ -361,7 +392,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         gi += g1.z;
         const xg_camera &c = cams[v];
         Proj64 P;
-        project64(m, s, q, c, (double)p.lowpass, P);
+        project64(m, s, G.R, c, (double)p.lowpass, P);
         double r[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) r[k] = (double)c.rot[k];
@@ -391,7 +422,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) Ms[3 * a + b] = P.R[3 * a + b] * (double)s[b];
+            for (int b = 0; b < 3; ++b) Ms[3 * a + b] = G.R[3 * a + b] * (double)s[b];
         double GA2[6];
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
@@ -405,11 +436,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const double gmab = P.A2[a] * GB[b] + P.A2[3 + a] * GB[3 + b];
-                gs[b] += gmab * P.R[3 * a + b];
+                gs[b] += gmab * G.R[3 * a + b];
                 GR[3 * a + b] = gmab * (double)s[b];
             }
         // rotation of the unit quaternion, then its normalisation
-        const double w = P.q[0], x = P.q[1], y = P.q[2], z = P.q[3];
+        const double w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
         double gw = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
         double gx = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5]
                          + z * GR[6] + w * GR[7] - 2 * x * GR[8]);
@@ -418,7 +449,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         double gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4]
                          + y * GR[5] + x * GR[6] + y * GR[7]);
         const double dot = w * gw + x * gx + y * gy + z * gz;
-        const double rqn = 1.0 / P.qn;
         gq[0] += (gw - w * dot) * rqn;
         gq[1] += (gx - x * dot) * rqn;
         gq[2] += (gy - y * dot) * rqn;
@@ -439,20 +469,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
 #pragma unroll
         for (int a = 0; a < 3; ++a) gm[a] += r[a] * gtx + r[3 + a] * gty + r[6 + a] * gtz;
     }
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            gm[a] += __shfl_xor(gm[a], o, kWave);
-            gs[a] += __shfl_xor(gs[a], o, kWave);
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) gq[a] += __shfl_xor(gq[a], o, kWave);
-        go += __shfl_xor(go, o, kWave);
-        gi += __shfl_xor(gi, o, kWave);
-        any = __shfl_xor((int)any, o, kWave) != 0 || any;
-    }
-    if (!any || sub != 0) return;
+    if (!any) return;
     float *om = gr.means + 3 * (int64_t)i;
     float *os = gr.scales + 3 * (int64_t)i;
     float *oq = gr.quats + 4 * (int64_t)i;
@@ -491,13 +508,14 @@ int grid_for(int64_t n, int threads, int max_blocks = 65536) {
 
 hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                              const Params &p, hipStream_t s) {
-    const int64_t nb = (ws.n_items + 255) / 256;
+    const int64_t nb = (ws.n_items + kPreThreads - 1) / kPreThreads;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     // depth partials live in the scan scratch; the count scan runs after
     // k_depth_range has consumed them
     uint32_t *part = ws.scan_tmp;
     if (nb > 0)
-        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)nb), dim3(256), 0, s, ws, g, cams, p, part);
+        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)nb), dim3(kPreThreads), 0, s, ws, g, cams, p,
+                           part);
     hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1024), 0, s, ws.hdr, part, (int)nb);
     return hipGetLastError();
 }
@@ -511,17 +529,9 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
 
 hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                                  const Params &p, const xg_grads &gr, hipStream_t s) {
-    // one lane per Gaussian measured fastest (spreading the views over 2-8
-    // lanes made the launch slower); the shuffled variants stay available
-    const int L = 1;
-    const int64_t nb = ((int64_t)ws.n * L + 255) / 256;
-    const dim3 grid((unsigned)(nb > 0 ? nb : 1));
-    switch (L) {
-        case 8: hipLaunchKernelGGL(k_preprocess_bwd<8>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
-        case 4: hipLaunchKernelGGL(k_preprocess_bwd<4>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
-        case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
-        default: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(256), 0, s, ws, g, cams, p, gr); break;
-    }
+    // one thread per Gaussian, summing its views in registers
+    const int nb = (ws.n + 255) / 256;
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, ws, g, cams, p, gr);
     return hipGetLastError();
 }
 
