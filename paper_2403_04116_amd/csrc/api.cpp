@@ -102,7 +102,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     L.offsets = o;            o = align_up(o + 4 * (size_t)ni);
     P.scan_tmp = o;           o = align_up(o + 4 * (size_t)(scan_words > part_words ? scan_words : part_words));
     for (int b = 0; b < 2; ++b) { P.ikeys[b] = o; o = align_up(o + 4 * (size_t)ni); }
-    for (int b = 0; b < 2; ++b) { P.ivals[b] = o; o = align_up(o + 4 * (size_t)ni); }
+    for (int b = 0; b < 2; ++b) { P.ivals[b] = o; o = align_up(o + 8 * (size_t)ni); }
     for (int b = 0; b < 2; ++b) { P.ptile[b] = o; o = align_up(o + 4 * (size_t)cap); }
     for (int b = 0; b < 2; ++b) { P.pval[b] = o; o = align_up(o + 4 * (size_t)cap); }
     P.ghist = o;              o = align_up(o + 4 * (size_t)kSortCtlWords);
@@ -128,7 +128,7 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.scan_tmp = (uint32_t *)(b + P.scan_tmp);
     for (int k = 0; k < 2; ++k) {
         w.ikeys[k] = (uint32_t *)(b + P.ikeys[k]);
-        w.ivals[k] = (uint32_t *)(b + P.ivals[k]);
+        w.ivals[k] = (uint64_t *)(b + P.ivals[k]);
         w.ptile[k] = (uint32_t *)(b + P.ptile[k]);
         w.pval[k] = (uint32_t *)(b + P.pval[k]);
     }

@@ -67,7 +67,7 @@ struct Ws {
     uint32_t *offsets;     // exclusive scan of icounts
     uint32_t *scan_tmp;
     uint32_t *ikeys[2];    // item sort keys (float32 depth bits; 0xffffffff when culled)
-    uint32_t *ivals[2];    // item sort values ((view, Gaussian) index)
+    uint64_t *ivals[2];    // item sort values: (view, Gaussian) index | tile rectangle << 32
     uint32_t *ptile[2];    // pair sort keys (global tile id)
     uint32_t *pval[2];     // pair sort values (Gaussian index)
     uint32_t *ghist;       // radix sort: digit histograms [kMaxPasses][kRadix], one 128-byte line each
@@ -102,6 +102,28 @@ constexpr float kInvLog2eHalf = 1.38629436111989061883f; // 2 ln 2
 
 // Preprocess workgroups: 256 threads, one per (view, Gaussian).
 constexpr int kPreThreads = 256;
+
+// The tile rectangle of a (view, Gaussian) item packed in 32 bits and
+// carried through the item sort, so the pair emission reads no record:
+// first tile column and row (10 bits each), extra columns and rows (5 bits
+// each), bit 30 set when the rectangle fits (else the record is read).
+__host__ __device__ __forceinline__ uint32_t pack_tile_rect(int tx0, int tx1, int ty0, int ty1) {
+    const int dx = tx1 - tx0, dy = ty1 - ty0;
+    if (tx0 < 0 || ty0 < 0 || tx0 >= 1024 || ty0 >= 1024 || dx < 0 || dy < 0 || dx >= 32 || dy >= 32)
+        return 0u;
+    return (1u << 30) | (uint32_t)tx0 | ((uint32_t)ty0 << 10) | ((uint32_t)dx << 20) | ((uint32_t)dy << 25);
+}
+struct TileRect {
+    int tx0, tx1, ty0, ty1;
+};
+__device__ __forceinline__ bool unpack_tile_rect(uint32_t r, TileRect &t) {
+    if (!(r & (1u << 30))) return false;
+    t.tx0 = (int)(r & 1023u);
+    t.ty0 = (int)((r >> 10) & 1023u);
+    t.tx1 = t.tx0 + (int)((r >> 20) & 31u);
+    t.ty1 = t.ty0 + (int)((r >> 25) & 31u);
+    return true;
+}
 
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;

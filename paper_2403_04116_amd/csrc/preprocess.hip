@@ -201,6 +201,7 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
         const float o = g.opacity[i];
         uint32_t count = 0;
         uint32_t key = 0xffffffffu;   // item sort key: depth bits, the largest when culled
+        uint32_t trect = 0;
         const KeyOut ko = key_path(m, s, q, o, c, p);
         if (ko.ok) {
             Gauss64 G64;
@@ -227,13 +228,14 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
             rec.d = make_float4(0.f, 0.f, 0.f, 0.f);
             const int T = p.tile;
             count = (uint32_t)((ko.xh / T - ko.xl / T + 1) * (ko.yh / T - ko.yl / T + 1));
+            trect = pack_tile_rect(ko.xl / T, ko.xh / T, ko.yl / T, ko.yh / T);
             dmin = dbits;
             dmax = dbits;
             key = dbits;
         }
         ws.counts[idx] = count;
         ws.ikeys[0][idx] = key;
-        ws.ivals[0][idx] = (uint32_t)idx;
+        ws.ivals[0][idx] = (uint64_t)idx | ((uint64_t)trect << 32);
         // clear this (view, Gaussian)'s 2-D gradient accumulator for the backward
         float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d) + 2 * idx;
         g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -317,24 +319,32 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
         s_range[1] = ws.offsets[jl] + ws.icounts[jl];
     }
     uint32_t cnt = 0, off = 0;
-    uint32_t idx = 0;
+    uint64_t val = 0;
     if (j < ws.n_items) {
         cnt = ws.icounts[j];
         off = ws.offsets[j];
-        idx = ws.ivals[ws.hdr->item_sel & 1][j];
+        val = ws.ivals[ws.hdr->item_sel & 1][j];
     }
     __syncthreads();
     const uint32_t base = s_range[0];
     const uint32_t total = s_range[1] - base;
     const bool staged = total <= (uint32_t)kEmitStage;
     if (cnt > 0) {
+        const uint32_t idx = (uint32_t)val;
         const int v = (int)(idx / (uint32_t)ws.n);
         const uint32_t i = idx - (uint32_t)v * (uint32_t)ws.n;
-        const int4 rc = ws.rec[idx].c;
         const xg_camera &c = cams[v];
         const int txn = (c.width + tile - 1) / tile;
-        const int tx0 = (rc.z & 0xffff) / tile, tx1 = (rc.z >> 16) / tile;
-        const int ty0 = (rc.w & 0xffff) / tile, ty1 = (rc.w >> 16) / tile;
+        TileRect tr;
+        if (!unpack_tile_rect((uint32_t)(val >> 32), tr)) {
+            // rectangle too large to pack: read it from the record
+            const int4 rc = ws.rec[idx].c;
+            tr.tx0 = (rc.z & 0xffff) / tile;
+            tr.tx1 = (rc.z >> 16) / tile;
+            tr.ty0 = (rc.w & 0xffff) / tile;
+            tr.ty1 = (rc.w >> 16) / tile;
+        }
+        const int tx0 = tr.tx0, tx1 = tr.tx1, ty0 = tr.ty0, ty1 = tr.ty1;
         if (staged) {
             uint32_t m = off - base;
             for (int ty = ty0; ty <= ty1; ++ty)

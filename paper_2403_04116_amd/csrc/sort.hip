@@ -42,6 +42,7 @@ struct Ctl {
 // digit clamps to the largest kept depth).
 struct ItemSort {
     using Key = uint32_t;
+    using Val = uint64_t;   // item index | packed tile rectangle << 32
     static __device__ __forceinline__ Ctl ctl(const Ws &ws) {
         Ctl c;
         const WsHeader *h = ws.hdr;
@@ -56,7 +57,14 @@ struct ItemSort {
         return ((min(key, c.dmax) - c.dmin) >> shift) & (kRadix - 1);
     }
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ikeys[b]; }
-    static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.ivals[b]; }
+    static __device__ __forceinline__ Val *vals(const Ws &ws, int b) { return ws.ivals[b]; }
+    // tile count of an item from its value (packed rectangle, else the count array)
+    static __device__ __forceinline__ uint32_t count_of(const Ws &ws, Val v) {
+        TileRect t;
+        if (unpack_tile_rect((uint32_t)(v >> 32), t))
+            return (uint32_t)((t.tx1 - t.tx0 + 1) * (t.ty1 - t.ty0 + 1));
+        return ws.counts[(uint32_t)v];
+    }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
     static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
     static constexpr bool kSkipConstant = true;
@@ -73,6 +81,7 @@ struct ItemSort {
 // Global tile ids of the pairs.
 struct PairSort {
     using Key = uint32_t;
+    using Val = uint32_t;
     static __device__ __forceinline__ Ctl ctl(const Ws &ws) {
         Ctl c;
         const WsHeader *h = ws.hdr;
@@ -88,7 +97,8 @@ struct PairSort {
         return (key >> shift) & (kRadix - 1);
     }
     static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ptile[b]; }
-    static __device__ __forceinline__ uint32_t *vals(const Ws &ws, int b) { return ws.pval[b]; }
+    static __device__ __forceinline__ Val *vals(const Ws &ws, int b) { return ws.pval[b]; }
+    static __device__ __forceinline__ uint32_t count_of(const Ws &, Val) { return 0; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPairSortThreads, kItems = kPairSortItems;
     static constexpr bool kGatherCounts = false;
@@ -191,7 +201,8 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     const int64_t parts = (c.n + kSortBlock - 1) / kSortBlock;
 
     __shared__ Key skeys[kSortBlock];
-    __shared__ uint32_t svals[kSortBlock];
+    using Val = typename S::Val;
+    __shared__ Val svals[kSortBlock];
     __shared__ uint32_t whist[kSortThreads / kWave][kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t goff[kRadix];
@@ -243,9 +254,9 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     const int lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     const Key *kin = S::keys(ws, in_sel);
-    const uint32_t *vin = S::vals(ws, in_sel);
+    const Val *vin = S::vals(ws, in_sel);
     Key key[kSortItems];
-    uint32_t val[kSortItems];
+    Val val[kSortItems];
     uint32_t rank[kSortItems];
     const int64_t wbase = base + (int64_t)w * (kSortBlock / (kSortThreads / kWave));
     // all loads first (indices clamped into range), so they overlap
@@ -356,7 +367,7 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     __syncthreads();
     const int64_t nvalid = min((int64_t)kSortBlock, c.n - base);
     Key *kout = S::keys(ws, in_sel ^ 1);
-    uint32_t *vout = S::vals(ws, in_sel ^ 1);
+    Val *vout = S::vals(ws, in_sel ^ 1);
 #pragma unroll 4
     for (int k = 0; k < kSortItems; ++k) {
         const int pos = k * kSortThreads + threadIdx.x;
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
             if (dst < (uint64_t)c.n) {   // always true unless a look-back gave up
                 kout[dst] = kk;
                 vout[dst] = svals[pos];
-                if (S::kGatherCounts && last_run) ws.icounts[dst] = ws.counts[svals[pos]];
+                if (S::kGatherCounts && last_run) ws.icounts[dst] = S::count_of(ws, svals[pos]);
             }
         }
     }
