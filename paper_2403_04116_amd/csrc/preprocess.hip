@@ -345,20 +345,23 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
             tr.ty1 = (rc.w >> 16) / tile;
         }
         const int tx0 = tr.tx0, tx1 = tr.tx1, ty0 = tr.ty0, ty1 = tr.ty1;
+        // at most cnt pairs (the slots the scan reserved), whatever the rectangle
         if (staged) {
-            uint32_t m = off - base;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    s_t[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
-                    s_v[m] = i;
+            uint32_t *st = s_t + (off - base);
+            uint32_t *sv = s_v + (off - base);
+            uint32_t m = 0;
+            for (int ty = ty0; ty <= ty1 && m < cnt; ++ty)
+                for (int tx = tx0; tx <= tx1 && m < cnt; ++tx) {
+                    st[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
+                    sv[m] = i;
                     ++m;
                 }
         } else {
             uint32_t *tt = ws.ptile[0] + off;
             uint32_t *vv = ws.pval[0] + off;
-            int m = 0;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
+            uint32_t m = 0;
+            for (int ty = ty0; ty <= ty1 && m < cnt; ++ty)
+                for (int tx = tx0; tx <= tx1 && m < cnt; ++tx) {
                     tt[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
                     vv[m] = i;
                     ++m;

@@ -394,6 +394,7 @@ __global__ __launch_bounds__(256) void k_ranges(Ws ws) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t t = tiles[i];
+        if (t >= (uint64_t)ws.total_tiles) continue;   // never, for pairs the emission wrote
         if (i == 0 || tiles[i - 1] != t) ws.ranges[2 * (int64_t)t] = (uint32_t)i;
         if (i == n - 1 || tiles[i + 1] != t) ws.ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
     }
