@@ -37,8 +37,9 @@ def sigmoid(x):
 
 def rirf(features, weights):
     """Eq. 3: intensity = sigmoid(sum_k lambda_k f_k); features (n, N_f)."""
-    f = np.asarray(features, np.float64).reshape(len(features), -1)
-    return sigmoid(f @ np.asarray(weights, np.float64))
+    w = np.atleast_1d(np.asarray(weights, np.float64))
+    f = np.asarray(features, np.float64).reshape(len(features), w.size)
+    return sigmoid(f @ w)
 
 
 def rirf_grad(features, weights, dl_dintensity):
