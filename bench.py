@@ -294,6 +294,32 @@ def main():
 
     value = w.n_views / (ms_batched * 1e-3)
 
+    # the radiation intensity response (Eq. 3, 16 features) on its own: forward
+    # and adjoint over all Gaussians, HBM bound
+    nf = 16
+    feats = torch.randn(w.n, nf, device=dev) * 0.3
+    wts = torch.ones(nf, device=dev)
+    inten = torch.empty(w.n, device=dev)
+    gfeat = torch.zeros(w.n, nf, device=dev)
+    r_ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for rep in range(3):
+        if rep == 2:
+            r_ev[0].record(stream)
+        X.xg_rirf_fwd(feats.data_ptr(), wts.data_ptr(), w.n, nf, inten.data_ptr(), sid)
+        if rep == 2:
+            r_ev[1].record(stream)
+        X.xg_rirf_bwd(feats.data_ptr(), wts.data_ptr(), w.n, nf, inten.data_ptr(), gfeat.data_ptr(), sid)
+        if rep == 2:
+            r_ev[2].record(stream)
+    torch.cuda.synchronize()
+    rf_ms, rb_ms = r_ev[0].elapsed_time(r_ev[1]), r_ev[1].elapsed_time(r_ev[2])
+    rirf_bytes_f = w.n * (4 * nf + 4)
+    rirf_bytes_b = w.n * (4 * nf + 4 + 8 * nf)
+    rirf = {"n_features": nf, "fwd_ms": rf_ms, "bwd_ms": rb_ms,
+            "fwd_frac_hbm": rirf_bytes_f / (rf_ms * 1e-3) / PEAK_HBM_BPS,
+            "bwd_frac_hbm": rirf_bytes_b / (rb_ms * 1e-3) / PEAK_HBM_BPS}
+    del feats, gfeat, inten
+
     if args.calibrate_copy > 0:
         # a plain copy of known size, for scaling the HBM byte counters
         nbytes = args.calibrate_copy << 20
@@ -361,6 +387,7 @@ def main():
         "batched_over_per_view": (value / per_view["value"]) if per_view else None,
         "kernels_ms": {"k_render_fwd": fwd_ms, "k_render_bwd": bwd_ms},
         "stages": stages,
+        "rirf": rirf,
         "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
                  "revisited": upto},
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define XG_ABI_VERSION 1
+#define XG_ABI_VERSION 2
 
 typedef enum {
     XG_OK = 0,
@@ -248,14 +248,31 @@ xg_status xg_preprocess_bwd(const xg_frame *f /* [host] */, const xg_gaussians *
  * [3][total pixels]. */
 xg_status xg_render_counts(const xg_frame *f /* [host] */, int32_t *counts, void *stream);
 
+/* Radiation intensity response (Eq. 3): each Gaussian has a feature
+ * vector f[n_features] and its intensity is sigmoid(sum_k w[k] f[k]) with
+ * constant weights w (the paper's lambda; it adopts 16 features).
+ * features: device float[n][n_features]; weights: device
+ * float[n_features]; intensity: device float[n].  EINVAL: null pointers,
+ * n < 0, n_features outside [1, XG_MAX_FEATURES]. */
+#define XG_MAX_FEATURES 64
+xg_status xg_rirf_fwd(const float *features, const float *weights, int32_t n, int32_t n_features,
+                      float *intensity, void *stream);
+/* Adjoint: grad_features[i][k] += dl_dintensity[i] * s (1 - s) * w[k] with
+ * s the intensity recomputed from the features (accumulates; the caller
+ * clears grad_features). */
+xg_status xg_rirf_bwd(const float *features, const float *weights, int32_t n, int32_t n_features,
+                      const float *dl_dintensity, float *grad_features, void *stream);
+
 /* Raw (unconstrained) trainable parameters, float32 SoA, contiguous:
  * means[n][3], log_scales[n][3] (scales = exp), quats[n][4] (the renderer
- * normalises), opacity_logit[n] (opacity = sigmoid), feature[n]
- * (radiation intensity = sigmoid(feature_weight * feature), Eq. 3 with one
- * feature). */
+ * normalises), opacity_logit[n] (opacity = sigmoid), features[n][n_features]
+ * (intensity = sigmoid(weights . features), Eq. 3); weights is the
+ * constant device float[n_features]. */
 typedef struct {
-    float *means, *log_scales, *quats, *opacity_logit, *feature;
+    float *means, *log_scales, *quats, *opacity_logit, *features;
+    const float *weights;
     int32_t n;
+    int32_t n_features;
 } xg_params;
 
 /* Adam settings.  The paper's (Sec. 4.1): beta1 0.9, beta2 0.999, eps
@@ -272,7 +289,6 @@ typedef struct {
     int32_t lr_means_steps;
     float lr_scales, lr_quats, lr_opacity, lr_feature;
     float eps;
-    float feature_weight;
     int32_t reserved;       /* 0 */
     double beta1, beta2;
 } xg_adam;
@@ -283,15 +299,17 @@ typedef struct {
  * value, m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); then writes the
  * activated copies scales[n][3], opacity[n], intensity[n] (means and quats
- * are used raw) and advances *step.  m and v are float[12 n] in the order
- * means, log_scales, quats, opacity_logit, feature; *step starts at 0.
+ * are used raw) and advances *step.  m and v are float[(11 + n_features) n]
+ * in the order means, log_scales, quats, opacity_logit, features; *step
+ * starts at 0.
  * The step count lives on the device so a captured step replays correctly.
  * gate (device, nullable): when it reads nonzero at execution time the
  * step is skipped (nothing written, *step unchanged); pass the frame's
  * status word (xg_ws_layout.status) so a step whose pairs overflowed the
  * capacity never reaches the parameters.  All array pointers device;
  * updates in place.  EINVAL: null pointers, beta outside [0, 1), eps < 0,
- * non-finite or negative rates, lr_means_steps < 1, reserved != 0. */
+ * non-finite or negative rates, lr_means_steps < 1, reserved != 0,
+ * n_features outside [1, XG_MAX_FEATURES]. */
 xg_status xg_adam_step(const xg_params *p /* [host] struct of device ptrs */,
                        const xg_grads *g /* [host] struct of device ptrs */, float *m, float *v,
                        int32_t *step, const xg_adam *c /* [host] */, float *scales, float *opacity,

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libxg.so")
 
 XG_OK, XG_EINVAL, XG_ECAPACITY, XG_EHIP = 0, 1, 2, 3
 XG_F_PERSISTENT = 1
-ABI_VERSION = 1
+ABI_VERSION = 2
+MAX_FEATURES = 64
 
 
 class XgError(RuntimeError):
@@ -59,15 +60,15 @@ class XgGrads(C.Structure):
 
 class XgParams(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity_logit", C.c_void_p), ("feature", C.c_void_p), ("n", C.c_int32)]
+                ("opacity_logit", C.c_void_p), ("features", C.c_void_p), ("weights", C.c_void_p),
+                ("n", C.c_int32), ("n_features", C.c_int32)]
 
 
 class XgAdam(C.Structure):
     _fields_ = [("lr_means_start", C.c_float), ("lr_means_end", C.c_float),
                 ("lr_means_steps", C.c_int32), ("lr_scales", C.c_float), ("lr_quats", C.c_float),
                 ("lr_opacity", C.c_float), ("lr_feature", C.c_float), ("eps", C.c_float),
-                ("feature_weight", C.c_float), ("reserved", C.c_int32), ("beta1", C.c_double),
-                ("beta2", C.c_double)]
+                ("reserved", C.c_int32), ("beta1", C.c_double), ("beta2", C.c_double)]
 
 
 class XgFrame(C.Structure):
@@ -127,6 +128,10 @@ _L.xg_render_fwd_store.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _
                                    C.c_int32, C.c_int64, _P]
 _L.xg_render_bwd_store.restype = _S
 _L.xg_render_bwd_store.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P, C.c_int32, C.c_int64, _P]
+_L.xg_rirf_fwd.restype = _S
+_L.xg_rirf_fwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P]
+_L.xg_rirf_bwd.restype = _S
+_L.xg_rirf_bwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, _P]
 _L.xg_l1_grad.restype = _S
 _L.xg_l1_grad.argtypes = [_P, _P, _P, C.c_int64, C.c_float, _P]
 
@@ -137,7 +142,7 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_layout_views", "xg_ws_layout_of", "xg_workspace_size", "xg_preprocess",
             "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
             "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
-            "xg_render_fwd_store", "xg_render_bwd_store")
+            "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd")
 MAX_STORE_SLOTS = 4096
 
 
@@ -200,6 +205,17 @@ def xg_render_fwd(frame: XgFrame, g: XgGaussians, image: int, final_t: int, n_co
                   stream: int = 0) -> None:
     _check(_L.xg_render_fwd(C.byref(frame), C.byref(g), image, final_t, n_contrib, stream),
            "xg_render_fwd")
+
+
+def xg_rirf_fwd(features: int, weights: int, n: int, n_features: int, intensity: int,
+                stream: int = 0) -> None:
+    _check(_L.xg_rirf_fwd(features, weights, n, n_features, intensity, stream), "xg_rirf_fwd")
+
+
+def xg_rirf_bwd(features: int, weights: int, n: int, n_features: int, dl_dintensity: int,
+                grad_features: int, stream: int = 0) -> None:
+    _check(_L.xg_rirf_bwd(features, weights, n, n_features, dl_dintensity, grad_features, stream),
+           "xg_rirf_bwd")
 
 
 def xg_store_size(frame: XgFrame, slots: int) -> int:

@@ -1,8 +1,14 @@
-// Fused optimiser step: gradients of the activated parameters -> raw
-// gradients (chain rule through exp / sigmoid) -> Adam (bias-corrected
-// moments, Kingma & Ba Algorithm 1) -> new raw parameters and the
-// activated copies the next rendering reads.  One thread per raw scalar;
-// purely HBM bound (about 28 bytes read and 16-20 written per scalar).
+// Radiation intensity response (Eq. 3) and the fused optimiser step.
+//
+// RIRF: intensity = sigmoid(w . f) per Gaussian, one thread per Gaussian.
+//
+// Adam: gradients of the activated parameters -> raw gradients (chain rule
+// through exp / sigmoid / the response) -> Adam (bias-corrected moments,
+// Kingma & Ba Algorithm 1) -> new raw parameters and the activated copies
+// the next rendering reads.  One thread per raw scalar for means, scales,
+// quaternions and opacity; one thread per Gaussian for its feature vector
+// (the intensity needs all of it).  HBM bound: about 28 bytes read and
+// 16-20 written per scalar.
 #include "common.h"
 
 #include <math.h>
@@ -10,6 +16,42 @@
 namespace xg {
 
 namespace {
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// Weights staged in LDS (at most XG_MAX_FEATURES).
+__device__ __forceinline__ void load_weights(const float *w, int nf, float *s_w) {
+    for (int k = threadIdx.x; k < nf; k += blockDim.x) s_w[k] = w[k];
+    __syncthreads();
+}
+
+__device__ __forceinline__ float rirf_dot(const float *f, const float *s_w, int nf) {
+    float acc = 0.0f;
+    for (int k = 0; k < nf; ++k) acc = fmaf(s_w[k], f[k], acc);
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void k_rirf_fwd(const float *features, const float *weights,
+                                                  int64_t n, int nf, float *intensity) {
+    __shared__ float s_w[XG_MAX_FEATURES];
+    load_weights(weights, nf, s_w);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    intensity[i] = sigmoidf(rirf_dot(features + i * nf, s_w, nf));
+}
+
+__global__ __launch_bounds__(256) void k_rirf_bwd(const float *features, const float *weights,
+                                                  int64_t n, int nf, const float *dl_di,
+                                                  float *grad_f) {
+    __shared__ float s_w[XG_MAX_FEATURES];
+    load_weights(weights, nf, s_w);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float s = sigmoidf(rirf_dot(features + i * nf, s_w, nf));
+    const float g = dl_di[i] * s * (1.0f - s);
+    float *gf = grad_f + i * nf;
+    for (int k = 0; k < nf; ++k) gf[k] += g * s_w[k];
+}
 
 struct AdamArgs {
     xg_params p;
@@ -23,15 +65,9 @@ struct AdamArgs {
     int64_t n;
 };
 
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
-
-// Raw scalar k of the concatenated [means 3n | log_scales 3n | quats 4n |
-// opacity_logit n | feature n] state.
-__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
-    const int64_t n = a.n;
-    const int64_t total = 12 * n;
-    // step t = counter + 1: bias corrections and the position rate schedule,
-    // in double once per block
+// Per-block step coefficients (bias corrections, position rate) in double
+// from the device step counter; false when the gate skips the step.
+__device__ __forceinline__ bool step_coefficients(const AdamArgs &a, float coef[3]) {
     __shared__ float s_coef[3];
     __shared__ int s_skip;
     if (threadIdx.x == 0) {
@@ -44,12 +80,35 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
                                f * log((double)a.c.lr_means_end));
     }
     __syncthreads();
-    if (s_skip) return;
-    const float bias1 = s_coef[0], bias2 = s_coef[1], lr_means = s_coef[2];
+    coef[0] = s_coef[0];
+    coef[1] = s_coef[1];
+    coef[2] = s_coef[2];
+    return !s_skip;
+}
+
+__device__ __forceinline__ float adam_update(const AdamArgs &a, int64_t k, float x, float grad,
+                                             float lr, float bias1, float bias2) {
+    const float m = a.b1 * a.m[k] + a.c1 * grad;
+    const float v = a.b2 * a.v[k] + a.c2 * grad * grad;
+    a.m[k] = m;
+    a.v[k] = v;
+    const float mhat = m / bias1;
+    const float vhat = v / bias2;
+    return x - lr * mhat / (sqrtf(vhat) + a.c.eps);
+}
+
+// Raw scalar k of the concatenated [means 3n | log_scales 3n | quats 4n |
+// opacity_logit n] state.
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+    const int64_t n = a.n;
+    const int64_t total = 11 * n;
+    float coef[3];
+    if (!step_coefficients(a, coef)) return;
+    const float bias1 = coef[0], bias2 = coef[1], lr_means = coef[2];
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
         float *param, grad, lr;
-        int kind;        // 0 identity, 1 exp, 2 sigmoid (opacity), 3 sigmoid(lambda f)
+        int kind;        // 0 identity, 1 exp, 2 sigmoid (opacity)
         int64_t e;       // index inside the group
         if (k < 3 * n) {
             e = k; param = a.p.means + e; grad = a.g.means[e]; lr = lr_means; kind = 0;
@@ -57,10 +116,8 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
             e = k - 3 * n; param = a.p.log_scales + e; grad = a.g.scales[e]; lr = a.c.lr_scales; kind = 1;
         } else if (k < 10 * n) {
             e = k - 6 * n; param = a.p.quats + e; grad = a.g.quats[e]; lr = a.c.lr_quats; kind = 0;
-        } else if (k < 11 * n) {
-            e = k - 10 * n; param = a.p.opacity_logit + e; grad = a.g.opacity[e]; lr = a.c.lr_opacity; kind = 2;
         } else {
-            e = k - 11 * n; param = a.p.feature + e; grad = a.g.intensity[e]; lr = a.c.lr_feature; kind = 3;
+            e = k - 10 * n; param = a.p.opacity_logit + e; grad = a.g.opacity[e]; lr = a.c.lr_opacity; kind = 2;
         }
         const float x = *param;
         // chain rule at the value the renderer used
@@ -69,29 +126,68 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
         } else if (kind == 2) {
             const float s = sigmoidf(x);
             grad *= s * (1.0f - s);
-        } else if (kind == 3) {
-            const float s = sigmoidf(a.c.feature_weight * x);
-            grad *= a.c.feature_weight * s * (1.0f - s);
         }
-        const float m = a.b1 * a.m[k] + a.c1 * grad;
-        const float v = a.b2 * a.v[k] + a.c2 * grad * grad;
-        a.m[k] = m;
-        a.v[k] = v;
-        const float mhat = m / bias1;
-        const float vhat = v / bias2;
-        const float xn = x - lr * mhat / (sqrtf(vhat) + a.c.eps);
+        const float xn = adam_update(a, k, x, grad, lr, bias1, bias2);
         *param = xn;
         if (kind == 1) a.scales[e] = expf(xn);
         else if (kind == 2) a.opacity[e] = sigmoidf(xn);
-        else if (kind == 3) a.intensity[e] = sigmoidf(a.c.feature_weight * xn);
     }
+}
+
+// Feature vector of Gaussian i: the response's chain rule at the current
+// features, Adam on each feature, then the new intensity.
+__global__ __launch_bounds__(256) void k_adam_features(AdamArgs a) {
+    __shared__ float s_w[XG_MAX_FEATURES];
+    const int nf = a.p.n_features;
+    load_weights(a.p.weights, nf, s_w);
+    float coef[3];
+    if (!step_coefficients(a, coef)) return;
+    const float bias1 = coef[0], bias2 = coef[1];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    float *f = a.p.features + i * nf;
+    const float s = sigmoidf(rirf_dot(f, s_w, nf));
+    const float gs = a.g.intensity[i] * s * (1.0f - s);
+    const int64_t k0 = 11 * a.n + i * nf;    // moments of this Gaussian's features
+    float acc = 0.0f;
+    for (int k = 0; k < nf; ++k) {
+        const float xn = adam_update(a, k0 + k, f[k], gs * s_w[k], a.c.lr_feature, bias1, bias2);
+        f[k] = xn;
+        acc = fmaf(s_w[k], xn, acc);
+    }
+    a.intensity[i] = sigmoidf(acc);
 }
 
 __global__ void k_step_advance(int32_t *step, const int32_t *gate) {
     if (threadIdx.x == 0 && (gate == nullptr || *gate == 0)) *step += 1;
 }
 
+unsigned grid_of(int64_t n) {
+    int64_t nb = (n + 255) / 256;
+    if (nb < 1) nb = 1;
+    if (nb > 65536) nb = 65536;
+    return (unsigned)nb;
+}
+
 }  // namespace
+
+hipError_t launch_rirf_fwd(const float *features, const float *weights, int64_t n, int nf,
+                           float *intensity, hipStream_t s) {
+    const int64_t nb = (n + 255) / 256;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_rirf_fwd, dim3((unsigned)nb), dim3(256), 0, s, features, weights, n, nf,
+                           intensity);
+    return hipGetLastError();
+}
+
+hipError_t launch_rirf_bwd(const float *features, const float *weights, int64_t n, int nf,
+                           const float *dl_di, float *grad_f, hipStream_t s) {
+    const int64_t nb = (n + 255) / 256;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_rirf_bwd, dim3((unsigned)nb), dim3(256), 0, s, features, weights, n, nf,
+                           dl_di, grad_f);
+    return hipGetLastError();
+}
 
 hipError_t launch_adam(const xg_params &p, const xg_grads &g, float *m, float *v, int32_t *step,
                        const xg_adam &c, float *scales, float *opacity, float *intensity,
@@ -99,10 +195,9 @@ hipError_t launch_adam(const xg_params &p, const xg_grads &g, float *m, float *v
     AdamArgs a{p, g, m, v, step, gate, c,
                (float)c.beta1, (float)(1.0 - c.beta1), (float)c.beta2, (float)(1.0 - c.beta2),
                scales, opacity, intensity, (int64_t)p.n};
-    const int64_t total = 12 * (int64_t)p.n;
-    int64_t nb = (total + 255) / 256;
-    if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adam, dim3(grid_of(11 * (int64_t)p.n)), dim3(256), 0, s, a);
+    const int64_t nb = ((int64_t)p.n + 255) / 256;
+    hipLaunchKernelGGL(k_adam_features, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step, gate);
     return hipGetLastError();
 }

@@ -429,16 +429,33 @@ xg_status xg_render_counts(const xg_frame *f, int32_t *counts, void *stream) {
     return hip_status(launch_render_counts(ws, f->cams_dev, p, counts, (hipStream_t)stream));
 }
 
+xg_status xg_rirf_fwd(const float *features, const float *weights, int32_t n, int32_t n_features,
+                      float *intensity, void *stream) {
+    if (n < 0 || n_features < 1 || n_features > XG_MAX_FEATURES) return XG_EINVAL;
+    if (n > 0 && (!features || !weights || !intensity)) return XG_EINVAL;
+    return hip_status(launch_rirf_fwd(features, weights, n, n_features, intensity, (hipStream_t)stream));
+}
+
+xg_status xg_rirf_bwd(const float *features, const float *weights, int32_t n, int32_t n_features,
+                      const float *dl_dintensity, float *grad_features, void *stream) {
+    if (n < 0 || n_features < 1 || n_features > XG_MAX_FEATURES) return XG_EINVAL;
+    if (n > 0 && (!features || !weights || !dl_dintensity || !grad_features)) return XG_EINVAL;
+    return hip_status(launch_rirf_bwd(features, weights, n, n_features, dl_dintensity, grad_features,
+                                      (hipStream_t)stream));
+}
+
 xg_status xg_adam_step(const xg_params *p, const xg_grads *g, float *m, float *v, int32_t *step,
                        const xg_adam *c, float *scales, float *opacity, float *intensity,
                        const int32_t *gate, void *stream) {
     if (!p || !g || !c || !step || p->n < 0) return XG_EINVAL;
-    if (!p->means || !p->log_scales || !p->quats || !p->opacity_logit || !p->feature) return XG_EINVAL;
+    if (!p->means || !p->log_scales || !p->quats || !p->opacity_logit || !p->features || !p->weights)
+        return XG_EINVAL;
+    if (p->n_features < 1 || p->n_features > XG_MAX_FEATURES) return XG_EINVAL;
     if (!g->means || !g->scales || !g->quats || !g->opacity || !g->intensity) return XG_EINVAL;
     if (!m || !v || !scales || !opacity || !intensity) return XG_EINVAL;
     if (!(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0)) return XG_EINVAL;
     if (c->reserved != 0) return XG_EINVAL;
-    if (!(c->eps >= 0.0f) || !isfinite(c->feature_weight) || c->lr_means_steps < 1) return XG_EINVAL;
+    if (!(c->eps >= 0.0f) || c->lr_means_steps < 1) return XG_EINVAL;
     if (!(c->lr_means_start > 0.0f) || !(c->lr_means_end > 0.0f)) return XG_EINVAL;
     const float lrs[6] = {c->lr_means_start, c->lr_means_end, c->lr_scales, c->lr_quats,
                           c->lr_opacity, c->lr_feature};

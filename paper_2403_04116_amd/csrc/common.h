@@ -174,6 +174,10 @@ hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_c
 hipError_t launch_l1_grad(const float *image, const float *target, float *out, int64_t n,
                           float scale, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_rirf_fwd(const float *features, const float *weights, int64_t n, int nf,
+                           float *intensity, hipStream_t s);
+hipError_t launch_rirf_bwd(const float *features, const float *weights, int64_t n, int nf,
+                           const float *dl_di, float *grad_f, hipStream_t s);
 hipError_t launch_adam(const xg_params &p, const xg_grads &g, float *m, float *v, int32_t *step,
                        const xg_adam &c, float *scales, float *opacity, float *intensity,
                        const int32_t *gate, hipStream_t s);

@@ -283,6 +283,35 @@ class DRRFunction(torch.autograd.Function):
                 grads["intensity"], None)
 
 
+def rirf(features: torch.Tensor, weights: torch.Tensor, stream=None) -> torch.Tensor:
+    """Eq. 3: intensity = sigmoid(weights . features) (xg_rirf_fwd)."""
+    n, nf = features.shape
+    out = torch.empty(n, dtype=torch.float32, device=features.device)
+    X.xg_rirf_fwd(features.data_ptr(), weights.data_ptr(), n, nf, out.data_ptr(), _stream(stream))
+    return out
+
+
+class RIRFFunction(torch.autograd.Function):
+    """Autograd wrapper of the radiation intensity response (weights are
+    constants, no gradient)."""
+
+    @staticmethod
+    def forward(ctx, features, weights):
+        features = features.contiguous()
+        weights = weights.contiguous()
+        ctx.save_for_backward(features, weights)
+        return rirf(features, weights)
+
+    @staticmethod
+    def backward(ctx, dl_di):
+        features, weights = ctx.saved_tensors
+        n, nf = features.shape
+        gf = torch.zeros_like(features)
+        X.xg_rirf_bwd(features.data_ptr(), weights.data_ptr(), n, nf, dl_di.contiguous().data_ptr(),
+                      gf.data_ptr(), _stream(None))
+        return gf, None
+
+
 def render(g: dict, frame: Frame):
     """Differentiable render of all views; returns the concatenated image."""
     image, _, _ = DRRFunction.apply(g["means"], g["scales"], g["quats"], g["opacity"],

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_status_strings():
-    assert P.xg_abi_version() == 1
+    assert P.xg_abi_version() == 2
     for st in (0, 1, 2, 3):
         assert X.status_string(st).startswith("XG_")
 
@@ -47,13 +47,13 @@ def test_struct_sizes_match_header():
     assert C.sizeof(X.XgFrame) == 80
     assert C.sizeof(X.XgAdam) == 56
     assert X.XgAdam.beta1.offset == 40
-    assert C.sizeof(X.XgParams) == 48
+    assert C.sizeof(X.XgParams) == 56
     assert C.sizeof(X.XgGrads) == 40
 
 
 def _adam_cfg(**kw):
     c = dict(lr_means_start=1.9e-4, lr_means_end=1.9e-6, lr_means_steps=20000, lr_scales=5e-3,
-             lr_quats=1e-3, lr_opacity=8e-3, lr_feature=2e-3, eps=1e-15, feature_weight=1.0,
+             lr_quats=1e-3, lr_opacity=8e-3, lr_feature=2e-3, eps=1e-15,
              reserved=0, beta1=0.9, beta2=0.999)
     c.update(kw)
     return X.XgAdam(**c)
@@ -64,7 +64,7 @@ def _adam_cfg(**kw):
                                  dict(lr_quats=float("nan")), dict(reserved=1)])
 def test_invalid_adam_settings_rejected_before_any_hip_call(bad):
     fake = 4096          # never dereferenced: validation fails first
-    p = X.XgParams(fake, fake, fake, fake, fake, 10)
+    p = X.XgParams(fake, fake, fake, fake, fake, fake, 10, 16)
     g = X.XgGrads(fake, fake, fake, fake, fake)
     with pytest.raises(X.XgError) as e:
         X.xg_adam_step(p, g, fake, fake, fake, _adam_cfg(**bad), fake, fake, fake, 0, 0)
@@ -214,3 +214,21 @@ def test_store_size_and_validation():
     with pytest.raises(X.XgError) as e:
         X.xg_render_fwd_store(f, g, 256, 256, 256, 256, 8, s8, 0)
     assert e.value.status == X.XG_EINVAL
+
+
+def test_invalid_feature_counts_rejected_before_any_hip_call():
+    fake = 4096
+    for nf in (0, -3, X.MAX_FEATURES + 1):
+        with pytest.raises(X.XgError) as e:
+            X.xg_rirf_fwd(fake, fake, 10, nf, fake, 0)
+        assert e.value.status == X.XG_EINVAL
+        with pytest.raises(X.XgError) as e:
+            X.xg_rirf_bwd(fake, fake, 10, nf, fake, fake, 0)
+        assert e.value.status == X.XG_EINVAL
+        p = X.XgParams(fake, fake, fake, fake, fake, fake, 10, nf)
+        g = X.XgGrads(fake, fake, fake, fake, fake)
+        with pytest.raises(X.XgError) as e:
+            X.xg_adam_step(p, g, fake, fake, fake, _adam_cfg(), fake, fake, fake, 0, 0)
+        assert e.value.status == X.XG_EINVAL
+    with pytest.raises(X.XgError):
+        X.xg_rirf_fwd(0, fake, 10, 16, fake, 0)          # null features

@@ -1,6 +1,7 @@
 """Fused Adam (xg_adam_step) against the FP64 optimiser oracle: raw
-parameters, moments and activated copies over several steps, inside a
-captured graph, and after a complete render + backward + update step."""
+parameters (16-feature intensity response), moments and activated copies
+over several steps, inside a captured graph, and after a complete render +
+backward + update step."""
 import math
 
 import numpy as np
@@ -16,13 +17,13 @@ pytestmark = pytest.mark.gpu
 RAWK = A.RAW
 
 
-def _raw(n, seed):
+def _raw(n, seed, nf):
     rng = np.random.default_rng(seed)
     return {"means": rng.uniform(-1, 1, (n, 3)).astype(np.float32),
             "log_scales": rng.normal(math.log(0.02), 0.3, (n, 3)).astype(np.float32),
             "quats": rng.normal(size=(n, 4)).astype(np.float32),
             "opacity_logit": rng.normal(size=n).astype(np.float32),
-            "feature": rng.normal(size=n).astype(np.float32)}
+            "features": (rng.normal(size=(n, nf)) * 0.3).astype(np.float32)}
 
 
 def _grads(n, seed):
@@ -34,15 +35,19 @@ def _grads(n, seed):
             "intensity": rng.normal(size=n).astype(np.float32)}
 
 
-def _gpu_opt(raw_np, lam):
+def _weights(nf):
+    return np.random.default_rng(nf).uniform(0.2, 1.5, nf).astype(np.float32)
+
+
+def _gpu_opt(raw_np, w_np):
     import torch
     from paper_2403_04116_amd.optim import FusedAdam
     raw = {k: torch.from_numpy(v.copy()).cuda() for k, v in raw_np.items()}
     act = {"means": raw["means"], "quats": raw["quats"],
            "scales": torch.empty_like(raw["log_scales"]),
            "opacity": torch.empty_like(raw["opacity_logit"]),
-           "intensity": torch.empty_like(raw["feature"])}
-    return FusedAdam(raw, act, feature_weight=lam)
+           "intensity": torch.empty(raw["means"].shape[0], device="cuda")}
+    return FusedAdam(raw, act, torch.from_numpy(w_np).cuda())
 
 
 def _check(opt, raw_o, act_o, m_o, v_o, lrs):
@@ -52,10 +57,13 @@ def _check(opt, raw_o, act_o, m_o, v_o, lrs):
     for k in RAWK:
         got = opt.raw[k].cpu().numpy().astype(np.float64)
         np.testing.assert_allclose(got, raw_o[k], rtol=2e-6, atol=1e-4 * lr)
+    n = opt.n
+    sizes = {"means": 3 * n, "log_scales": 3 * n, "quats": 4 * n, "opacity_logit": n,
+             "features": opt.n_features * n}
     off = 0
     mm, vv = opt.m.cpu().numpy(), opt.v.cpu().numpy()
     for k in RAWK:
-        sz = m_o[k].size
+        sz = sizes[k]
         # float32 moments: cancellation in beta1 * m + (1 - beta1) * g leaves
         # absolute noise relative to the group's largest moment
         np.testing.assert_allclose(mm[off:off + sz], m_o[k].reshape(-1), rtol=1e-5,
@@ -67,38 +75,40 @@ def _check(opt, raw_o, act_o, m_o, v_o, lrs):
         np.testing.assert_allclose(opt.act[k].cpu().numpy(), act_o[k], rtol=1e-5, atol=1e-7)
 
 
-@pytest.mark.parametrize("lam", [1.0, 0.7])
-def test_adam_steps_match_oracle(lam):
+@pytest.mark.parametrize("nf", [16, 1, 37])
+def test_adam_steps_match_oracle(nf):
     import torch
     n = 5003
-    raw_np = _raw(n, 1)
-    opt = _gpu_opt(raw_np, lam)
+    raw_np = _raw(n, 1, nf)
+    w = _weights(nf)
+    opt = _gpu_opt(raw_np, w)
     cur = {k: v.astype(np.float64) for k, v in raw_np.items()}
     m = {k: np.zeros_like(v) for k, v in cur.items()}
     v = {k: np.zeros_like(x) for k, x in cur.items()}
+    prev = cur
     for t in range(1, 5):
         g = _grads(n, 10 + t)
-        note(f"adam step {t}")
+        note(f"adam step {t}, {nf} features")
         opt.step({k: torch.from_numpy(x).cuda() for k, x in g.items()})
         lrs = A.paper_lrs(t)
         # the oracle steps from the GPU's float32 parameters of the previous step
-        prev = {k: opt_prev[k] for k in RAWK} if t > 1 else cur
-        cur, m, v, act = A.adam_step(prev, g, m, v, t, lrs, feature_weight=lam)
+        cur, m, v, act = A.adam_step(prev, g, m, v, t, lrs, w.astype(np.float64))
         _check(opt, cur, act, m, v, lrs)
-        opt_prev = {k: opt.raw[k].cpu().numpy().astype(np.float64) for k in RAWK}
+        prev = {k: opt.raw[k].cpu().numpy().astype(np.float64) for k in RAWK}
     assert int(opt.step_count.item()) == 4
 
 
 def test_adam_in_captured_graph_advances_the_step():
     import torch
-    n = 2048
-    raw_np = _raw(n, 2)
+    n, nf = 2048, 16
+    raw_np = _raw(n, 2, nf)
+    w = _weights(nf)
     g = _grads(n, 3)
     gt = {k: torch.from_numpy(x).cuda() for k, x in g.items()}
-    eager = _gpu_opt(raw_np, 1.0)
+    eager = _gpu_opt(raw_np, w)
     for _ in range(4):
         eager.step(gt)
-    cap = _gpu_opt(raw_np, 1.0)
+    cap = _gpu_opt(raw_np, w)
     cap.step(gt)                      # step 1 eager (warm-up)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -138,16 +148,17 @@ def test_render_backward_adam_step_matches_oracle():
     img, ft, nc = frame.render_fwd(opt.act)
     grads = frame.backward(opt.act, torch.from_numpy(up).cuda(), ft, nc)
     raw0 = {k: t.cpu().numpy().astype(np.float64) for k, t in opt.raw.items()}
+    w = opt.weights.cpu().numpy().astype(np.float64)
     opt.step(grads)
     torch.cuda.synchronize()
     gref = O.backward(g_np, cams_o, st_o, up)
     z = {k: np.zeros_like(x) for k, x in raw0.items()}
     new, m, v, act = A.adam_step(raw0, {"means": gref["means"], "scales": gref["scales"],
                                         "quats": gref["quats"], "opacity": gref["opacity"],
-                                        "intensity": gref["intensity"]}, z, z, 1, A.paper_lrs(1))
+                                        "intensity": gref["intensity"]}, z, z, 1, A.paper_lrs(1), w)
     # the first step moves each parameter by lr * sign(raw gradient): compare
     # where the oracle's gradient is well above the renderer's atomic-order noise
-    rg = A.raw_grads(raw0, gref)
+    rg = A.raw_grads(raw0, gref, w)
     for k in RAWK:
         got = opt.raw[k].cpu().numpy().astype(np.float64)
         big = np.abs(rg[k]) > 1e-2 * np.abs(rg[k]).max()
