@@ -62,11 +62,11 @@ def parse():
 
 
 def kernel_source_hash() -> str:
-    """Hash of the blend kernels' source; a stored HBM-traffic figure is only
-    reported while it matches."""
+    """Hash of the blend kernels' source file; a stored HBM-traffic figure is
+    only reported while it matches."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("render.hip", "common.h"):
+    for f in ("render.hip",):
         with open(os.path.join(ROOT, "paper_2403_04116_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

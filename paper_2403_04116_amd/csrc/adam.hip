@@ -6,7 +6,7 @@
 // through exp / sigmoid / the response) -> Adam (bias-corrected moments,
 // Kingma & Ba Algorithm 1) -> new raw parameters and the activated copies
 // the next rendering reads.  One thread per raw scalar for means, scales,
-// quaternions and opacity; one thread per Gaussian for its feature vector
+// quaternions and opacity; one lane per feature for the feature vectors
 // (the intensity needs all of it).  HBM bound: about 28 bytes read and
 // 16-20 written per scalar.
 #include "common.h"
@@ -134,8 +134,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     }
 }
 
-// Feature vector of Gaussian i: the response's chain rule at the current
-// features, Adam on each feature, then the new intensity.
+// Feature vectors: G lanes per Gaussian (G = the feature count rounded up
+// to a power of two, at most 64), lane k owning feature k, so every access
+// is coalesced.  The response's chain rule at the current features (the
+// inner product summed across the G lanes with shuffles), Adam on each
+// feature, then the new intensity from the updated features.
+template <int G>
 __global__ __launch_bounds__(256) void k_adam_features(AdamArgs a) {
     __shared__ float s_w[XG_MAX_FEATURES];
     const int nf = a.p.n_features;
@@ -143,19 +147,28 @@ __global__ __launch_bounds__(256) void k_adam_features(AdamArgs a) {
     float coef[3];
     if (!step_coefficients(a, coef)) return;
     const float bias1 = coef[0], bias2 = coef[1];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    float *f = a.p.features + i * nf;
-    const float s = sigmoidf(rirf_dot(f, s_w, nf));
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / G;
+    const int k = (int)(t % G);
+    if (i >= a.n) return;        // whole groups leave together
+    const bool own = k < nf;
+    const float wk = own ? s_w[k] : 0.0f;
+    float *f = a.p.features + i * nf + k;
+    const float x = own ? *f : 0.0f;
+    float dot = wk * x;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) dot += __shfl_xor(dot, o, kWave);
+    const float s = sigmoidf(dot);
     const float gs = a.g.intensity[i] * s * (1.0f - s);
-    const int64_t k0 = 11 * a.n + i * nf;    // moments of this Gaussian's features
-    float acc = 0.0f;
-    for (int k = 0; k < nf; ++k) {
-        const float xn = adam_update(a, k0 + k, f[k], gs * s_w[k], a.c.lr_feature, bias1, bias2);
-        f[k] = xn;
-        acc = fmaf(s_w[k], xn, acc);
+    float xn = 0.0f;
+    if (own) {
+        xn = adam_update(a, 11 * a.n + i * nf + k, x, gs * wk, a.c.lr_feature, bias1, bias2);
+        *f = xn;
     }
-    a.intensity[i] = sigmoidf(acc);
+    float dn = wk * xn;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) dn += __shfl_xor(dn, o, kWave);
+    if (k == 0) a.intensity[i] = sigmoidf(dn);
 }
 
 __global__ void k_step_advance(int32_t *step, const int32_t *gate) {
@@ -196,8 +209,20 @@ hipError_t launch_adam(const xg_params &p, const xg_grads &g, float *m, float *v
                (float)c.beta1, (float)(1.0 - c.beta1), (float)c.beta2, (float)(1.0 - c.beta2),
                scales, opacity, intensity, (int64_t)p.n};
     hipLaunchKernelGGL(k_adam, dim3(grid_of(11 * (int64_t)p.n)), dim3(256), 0, s, a);
-    const int64_t nb = ((int64_t)p.n + 255) / 256;
-    hipLaunchKernelGGL(k_adam_features, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, a);
+    int G = 1;
+    while (G < p.n_features) G *= 2;
+    const int64_t nb = ((int64_t)p.n * G + 255) / 256;
+    const dim3 grid((unsigned)(nb > 0 ? nb : 1));
+    switch (G) {
+        case 1: hipLaunchKernelGGL(k_adam_features<1>, grid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_adam_features<2>, grid, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_adam_features<4>, grid, dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_adam_features<8>, grid, dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_adam_features<16>, grid, dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(k_adam_features<32>, grid, dim3(256), 0, s, a); break;
+        case 64: hipLaunchKernelGGL(k_adam_features<64>, grid, dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step, gate);
     return hipGetLastError();
 }
