@@ -14,7 +14,10 @@ one view per launch sequence, looped over the views.  Prints one JSON line.
 --workload 5 is the training-scale case (1M Gaussians, 16 views of
 512 x 512, anisotropic scales) whose step also runs the fused Adam update;
 --store SLOTS switches to the stored-transmittance forward/backward.  Both
-report the peak device memory of the step.
+report the peak device memory of the step.  --loss eq11 takes the upstream
+gradient from the full Eq. 11 objective (0.8 L1 + 0.2 SSIM term, fused
+kernels) instead of L1 alone; every run also times that objective on its
+own ("loss_eq11").
 """
 from __future__ import annotations
 
@@ -36,6 +39,9 @@ FLOPS_BLEND = 6          # blending a contributor (transmittance update, test, a
 FLOPS_ADJOINT = 28       # adjoint of one contributor (transmittance recovery, 7 gradients)
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
 PEAK_HBM_BPS = 8.0e12     # MI355X HBM3E
+# Eq. 11 loss gradient, algorithmic bytes per pixel: image + target read twice
+# (16), three SSIM derivative maps written then read (24), dl written (4)
+LOSS_BYTES_PER_PX = 44
 
 
 def parse():
@@ -56,6 +62,9 @@ def parse():
                     help="stored-transmittance variant with SLOTS per pixel (0: divide back)")
     ap.add_argument("--adam", type=int, default=-1,
                     help="run the fused Adam update in every step (1/0; default: on for workload 5)")
+    ap.add_argument("--loss", choices=("l1", "eq11"), default="l1",
+                    help="upstream gradient of the step: L1 alone, or the Eq. 11 objective "
+                         "(0.8 L1 + 0.2 SSIM term, fused kernels)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run 3 plain device copies of MB MiB (counter calibration)")
     return ap.parse_args()
@@ -121,13 +130,15 @@ def main():
     store = frame.new_store(args.store) if args.store > 0 else None
     out = frame.new_outputs()
     dl = torch.empty(npx, dtype=torch.float32, device=dev)
+    loss_val = torch.zeros(1, dtype=torch.float32, device=dev)
     grads = frame.new_grads(g)
     gs = P.drr.gaussians_struct(g)
     gr = P.XgGrads(*(grads[k].data_ptr() for k in P.drr.PARAMS))
     sid = int(stream.cuda_stream)
     image, final_t, n_contrib = out
     # per-stage HIP events on the launch stream: marks[k] follows stage k
-    STAGES = ["zero_grads", "preprocess", "bin_sort", "render_fwd", "l1_grad", "render_bwd",
+    loss_stage = "l1_grad" if args.loss == "l1" else "loss_grad"
+    STAGES = ["zero_grads", "preprocess", "bin_sort", "render_fwd", loss_stage, "render_bwd",
               "preprocess_bwd"] + (["adam"] if opt is not None else [])
     marks = []
 
@@ -154,7 +165,11 @@ def main():
                                   n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
                                   store.view.numel(), sid)
         mark(record, row)
-        P.xg_l1_grad(image.data_ptr(), target.data_ptr(), dl.data_ptr(), npx, scale, sid)
+        if args.loss == "l1":
+            P.xg_l1_grad(image.data_ptr(), target.data_ptr(), dl.data_ptr(), npx, scale, sid)
+        else:
+            X.xg_loss_grad(frame.frame, image.data_ptr(), target.data_ptr(), 0.2, dl.data_ptr(),
+                           loss_val.data_ptr(), sid)
         mark(record, row)
         if store is None:
             P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
@@ -221,6 +236,7 @@ def main():
                      + npairs * (8 + 4 + 16 * pair_passes + 4) + 8 * frame.total_tiles),
         "render_fwd": ("alu", fwd_flops),
         "l1_grad": ("hbm", 12 * npx),
+        "loss_grad": ("hbm", LOSS_BYTES_PER_PX * npx),
         "render_bwd": ("alu", bwd_flops),
         "preprocess_bwd": ("hbm", 32 * n_items + 144 * w.n),
         "adam": ("hbm", 12 * w.n * 30),
@@ -320,6 +336,20 @@ def main():
             "bwd_frac_hbm": rirf_bytes_b / (rb_ms * 1e-3) / PEAK_HBM_BPS}
     del feats, gfeat, inten
 
+    # the Eq. 11 objective (0.8 L1 + 0.2 SSIM term) and its gradient on its own
+    l_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for rep in range(4):
+        if rep == 3:
+            l_ev[0].record(stream)
+        X.xg_loss_grad(frame.frame, image.data_ptr(), target.data_ptr(), 0.2, dl.data_ptr(),
+                       loss_val.data_ptr(), sid)
+        if rep == 3:
+            l_ev[1].record(stream)
+    torch.cuda.synchronize()
+    l_ms = l_ev[0].elapsed_time(l_ev[1])
+    loss_eq11 = {"ms": l_ms, "loss": float(loss_val.item()),
+                 "frac_hbm": LOSS_BYTES_PER_PX * npx / (l_ms * 1e-3) / PEAK_HBM_BPS}
+
     if args.calibrate_copy > 0:
         # a plain copy of known size, for scaling the HBM byte counters
         nbytes = args.calibrate_copy << 20
@@ -373,7 +403,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.describe()}, L1, fwd+bwd" + ("+Adam" if opt is not None else ""),
+        "config": {"workload": f"{w.describe()}, "
+                               + ("L1" if args.loss == "l1" else "Eq.11 L1+SSIM (gamma 0.2)")
+                               + ", fwd+bwd" + ("+Adam" if opt is not None else ""),
                    "gaussians": w.n, "views": w.n_views,
                    "detector": "x".join(map(str, w.sizes[0])) if len(set(w.sizes)) == 1 else "mixed",
                    "tile": args.tile, "lds_batch": args.lds, "persistent": bool(args.persistent),
@@ -388,6 +420,7 @@ def main():
         "kernels_ms": {"k_render_fwd": fwd_ms, "k_render_bwd": bwd_ms},
         "stages": stages,
         "rirf": rirf,
+        "loss_eq11": loss_eq11,
         "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
                  "revisited": upto},
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),

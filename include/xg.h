@@ -315,6 +315,20 @@ xg_status xg_adam_step(const xg_params *p /* [host] struct of device ptrs */,
                        int32_t *step, const xg_adam *c /* [host] */, float *scales, float *opacity,
                        float *intensity, const int32_t *gate, void *stream);
 
+/* Training objective of Eq. 11, L = (1 - gamma) L1 + gamma L_SSIM (the
+ * paper's gamma is 0.2), and its gradient with respect to the rendered
+ * images, for every view of the frame (image and target have the image
+ * layout).  L1 is the mean absolute difference over all pixels (sign(0) =
+ * 0); L_SSIM = 1 - the mean of the SSIM map of Wang et al., each view's map
+ * over its own image with an 11 x 11 Gaussian window (standard deviation
+ * 1.5), zero padding, C1 = 0.01^2, C2 = 0.03^2.  Writes dl_dimage; if loss
+ * (device float, nullable) is given, writes L there (per-tile shares added
+ * in double in a fixed order: deterministic).  Uses the frame's workspace
+ * for three per-pixel maps.  EINVAL: gamma outside [0, 1], null
+ * images. */
+xg_status xg_loss_grad(const xg_frame *f /* [host] */, const float *image, const float *target,
+                       float gamma, float *dl_dimage, float *loss, void *stream);
+
 /* L1 term of Eq. 11: dl_dimage[p] = scale * sign(image[p] - target[p])
  * (0 where equal), for n_pixels pixels. */
 xg_status xg_l1_grad(const float *image, const float *target, float *dl_dimage,

@@ -132,6 +132,8 @@ _L.xg_rirf_fwd.restype = _S
 _L.xg_rirf_fwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P]
 _L.xg_rirf_bwd.restype = _S
 _L.xg_rirf_bwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, _P]
+_L.xg_loss_grad.restype = _S
+_L.xg_loss_grad.argtypes = [C.POINTER(XgFrame), _P, _P, C.c_float, _P, _P, _P]
 _L.xg_l1_grad.restype = _S
 _L.xg_l1_grad.argtypes = [_P, _P, _P, C.c_int64, C.c_float, _P]
 
@@ -142,7 +144,8 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_layout_views", "xg_ws_layout_of", "xg_workspace_size", "xg_preprocess",
             "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
             "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
-            "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd")
+            "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd",
+            "xg_loss_grad")
 MAX_STORE_SLOTS = 4096
 
 
@@ -254,6 +257,12 @@ def xg_render_counts(frame: XgFrame, counts: int, stream: int = 0) -> None:
 def xg_l1_grad(image: int, target: int, dl_dimage: int, n_pixels: int, scale: float,
                stream: int = 0) -> None:
     _check(_L.xg_l1_grad(image, target, dl_dimage, n_pixels, scale, stream), "xg_l1_grad")
+
+
+def xg_loss_grad(frame: XgFrame, image: int, target: int, gamma: float, dl_dimage: int,
+                 loss: int = 0, stream: int = 0) -> None:
+    _check(_L.xg_loss_grad(C.byref(frame), image, target, gamma, dl_dimage, loss or None, stream),
+           "xg_loss_grad")
 
 
 def xg_adam_step(params: XgParams, grads: XgGrads, m: int, v: int, step: int, cfg: XgAdam,

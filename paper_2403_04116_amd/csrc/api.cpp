@@ -68,7 +68,7 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 
 struct Plan {
     xg_ws_layout lay;
-    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, lookback[2], tile_order;
+    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, lookback[2], tile_order, ssim;
     int64_t total_px, total_tiles, n_items;
     int32_t item_blocks, pair_blocks, tile_bits, pair_passes;
 };
@@ -110,6 +110,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
     L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
     P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
+    P.ssim = o;               o = align_up(o + 12 * (size_t)P.total_px + 4 * (size_t)loss_tiles(f->cams, f->n_views));
     L.pair_tiles = P.ptile[P.pair_passes & 1];
     L.pair_values = P.pval[P.pair_passes & 1];
     L.total = o;
@@ -139,6 +140,7 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.ranges = (uint32_t *)(b + P.lay.ranges);
     w.grad2d = (float *)(b + P.lay.grad2d);
     w.tile_order = (int32_t *)(b + P.tile_order);
+    w.ssim = (float *)(b + P.ssim);
     w.cap = f->pair_capacity;
     w.n_items = P.n_items;
     w.total_tiles = P.total_tiles;
@@ -427,6 +429,18 @@ xg_status xg_render_counts(const xg_frame *f, int32_t *counts, void *stream) {
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
     return hip_status(launch_render_counts(ws, f->cams_dev, p, counts, (hipStream_t)stream));
+}
+
+xg_status xg_loss_grad(const xg_frame *f, const float *image, const float *target, float gamma,
+                       float *dl_dimage, float *loss, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!image || !target || !dl_dimage) return XG_EINVAL;
+    if (!(gamma >= 0.0f && gamma <= 1.0f)) return XG_EINVAL;
+    const Ws ws = resolve(f, P);
+    return hip_status(launch_loss_grad(ws, f->cams_dev, loss_tiles(f->cams, f->n_views), image, target,
+                                       gamma, dl_dimage, loss, (hipStream_t)stream));
 }
 
 xg_status xg_rirf_fwd(const float *features, const float *weights, int32_t n, int32_t n_features,

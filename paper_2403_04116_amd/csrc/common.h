@@ -75,6 +75,8 @@ struct Ws {
     uint64_t *lookback[2]; // radix sort: per (partition, digit) aggregate / prefix words
     uint32_t *ranges;
     float *grad2d;
+    float *ssim;           // loss: three per-pixel SSIM partial-derivative maps, then one
+                           // loss share per 48 x 8 loss strip
     int32_t *tile_order;   // persistent queue: tiles in work order
     int64_t cap;
     int64_t n_items;       // n_views * n
@@ -171,6 +173,10 @@ hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Param
                                 int32_t *counts, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                                  const Params &p, const xg_grads &gr, hipStream_t s);
+int64_t loss_tiles(const xg_camera *cams_host, int n_views);
+hipError_t launch_loss_grad(const Ws &ws, const xg_camera *cams_dev, int64_t tiles,
+                            const float *image, const float *target, float gamma, float *dl,
+                            float *loss, hipStream_t s);
 hipError_t launch_l1_grad(const float *image, const float *target, float *out, int64_t n,
                           float scale, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

@@ -237,6 +237,18 @@ class Frame:
         X.xg_render_counts(self.frame, out.data_ptr(), _stream(stream))
         return out
 
+    def loss_grad(self, image: torch.Tensor, target: torch.Tensor, gamma: float = 0.2, out=None,
+                  loss: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """dL/dI of the Eq. 11 objective (1 - gamma) L1 + gamma L_SSIM over all
+        views; writes L into ``loss`` (one device float) when given."""
+        for t in (image, target):
+            if t.dtype != torch.float32 or t.numel() != self.total_pixels or not t.is_contiguous():
+                raise ValueError("image and target must be contiguous float32 of total_pixels")
+        out = torch.empty_like(image) if out is None else out
+        X.xg_loss_grad(self.frame, image.data_ptr(), target.data_ptr(), gamma, out.data_ptr(),
+                       loss.data_ptr() if loss is not None else 0, _stream(stream))
+        return out
+
     def split(self, flat: torch.Tensor):
         """Per-view (H, W) views of a concatenated per-pixel buffer."""
         out, o = [], 0

@@ -171,6 +171,14 @@ def test_invalid_frames_rejected_before_any_hip_call():
         P.xg_preprocess(f4, X.XgGaussians(0, 0, 0, 0, 0, 100))
     with pytest.raises(X.XgError):
         P.xg_l1_grad(0, 0, 0, 10, 1.0)
+    # loss gradient: null images and gamma outside [0, 1] fail before any HIP call
+    with pytest.raises(X.XgError) as e:
+        X.xg_loss_grad(f4, 0, 4096, 0.2, 8192)
+    assert e.value.status == X.XG_EINVAL
+    for gamma in (-0.1, 1.5, float("nan")):
+        with pytest.raises(X.XgError) as e:
+            X.xg_loss_grad(f4, 4096, 4096, gamma, 8192)
+        assert e.value.status == X.XG_EINVAL
 
 
 def test_package_fails_loudly_without_library(tmp_path):
