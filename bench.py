@@ -18,6 +18,11 @@ report the peak device memory of the step.  --loss eq11 takes the upstream
 gradient from the full Eq. 11 objective (0.8 L1 + 0.2 SSIM term, fused
 kernels) instead of L1 alone; every run also times that objective on its
 own ("loss_eq11").
+
+"acui_forward" is the forward-only scan of the ACUI-initialised model
+(Sec. 3.3, Eq. 13 grid of 35^3 centres, 100 views of 512 x 512 over 0-180
+degrees), batched and per view: the paper's inference measurement on a
+synthetic stand-in.  --no-acui skips it, --only-acui runs nothing else.
 """
 from __future__ import annotations
 
@@ -65,9 +70,107 @@ def parse():
     ap.add_argument("--loss", choices=("l1", "eq11"), default="l1",
                     help="upstream gradient of the step: L1 alone, or the Eq. 11 objective "
                          "(0.8 L1 + 0.2 SSIM term, fused kernels)")
+    ap.add_argument("--no-acui", action="store_true",
+                    help="skip the forward-only scan of the ACUI-initialised model")
+    ap.add_argument("--only-acui", action="store_true",
+                    help="run only the forward-only ACUI scan (prints its JSON object)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run 3 plain device copies of MB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def acui_forward(args, dev, stream, st) -> dict:
+    """Forward-only scan of the ACUI-initialised model (the paper's inference
+    measurement on a synthetic stand-in): centres on the Eq. 13 grid made by
+    the library, attributes from the seeded generator, 100 views of 512 x 512
+    evenly over 0-180 degrees.  One pass = preprocess + binning/sort +
+    forward blending of all views; batched (one launch sequence) and per view
+    (one launch sequence per view, the paper's one-projection-per-frame)."""
+    import numpy as np
+    import torch
+
+    import scenes as S
+    import paper_2403_04116_amd as P
+    from paper_2403_04116_amd import _lib as X
+
+    w = S.workload(6)
+    n = X.xg_acui_count(S.ACUI_SIZE, S.ACUI_GRID, S.ACUI_D)
+    attrs = S.attributes(n, w.log_scale_mean, w.log_scale_std, w.seeds["scene"])
+    g = {k: torch.from_numpy(v).to(dev) for k, v in attrs.items()}
+    g["means"] = P.acui_means(S.ACUI_SIZE, S.ACUI_GRID, S.ACUI_D, device=dev)
+    D = S.DETECTOR_SIDE
+    cams = P.cameras(w.angles, w.sizes, S.L_SO, S.L_SD, D, D)
+    sid = int(stream.cuda_stream)
+    gs = P.drr.gaussians_struct(g)
+    frame = P.Frame(n, cams, st, device=dev)
+    n_pairs = frame.fit_capacity(g)
+    image, final_t, n_contrib = frame.new_outputs()
+    names = ["preprocess", "bin_sort", "render_fwd"]
+    rows = []
+
+    def one_pass(record: bool):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        calls = [lambda: P.xg_preprocess(frame.frame, gs, sid),
+                 lambda: P.xg_bin_sort(frame.frame, sid),
+                 lambda: P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
+                                         n_contrib.data_ptr(), sid)]
+        if record:
+            ev[0].record(stream)
+        for k, c in enumerate(calls):
+            c()
+            if record:
+                ev[k + 1].record(stream)
+        if record:
+            rows.append(ev)
+
+    for _ in range(args.warmup):
+        one_pass(False)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        one_pass(True)
+    torch.cuda.synchronize()
+    assert frame.status() == 0, "pair capacity exceeded in the ACUI scan"
+    ms = float(np.mean([r[0].elapsed_time(r[3]) for r in rows]))
+    stages = {nm: float(np.mean([r[k].elapsed_time(r[k + 1]) for r in rows])) for k, nm in enumerate(names)}
+    out = {"workload": f"ACUI grid {S.ACUI_GRID[0]}^3 voxels, d={S.ACUI_D:g} (Eq. 13): {n} Gaussians, "
+                       f"{w.n_views} views of 512x512 over 0-180 deg, forward only",
+           "gaussians": n, "views": w.n_views, "pairs": int(n_pairs), "ms_per_pass": ms,
+           "views_per_s": w.n_views / (ms * 1e-3), "stages_ms": stages,
+           "paper_fps_context": "148 fps, one projection per frame, trained scenes, RTX 8000 (Tab. 1)"}
+    if not args.no_per_view:
+        frames = []
+        off = 0
+        for v in range(w.n_views):
+            f = P.Frame(n, [cams[v]], st, device=dev)
+            f.fit_capacity(g)
+            npx = w.sizes[v][0] * w.sizes[v][1]
+            frames.append((f, image[off:off + npx], final_t[off:off + npx], n_contrib[off:off + npx]))
+            off += npx
+
+        def per_view_pass():
+            for f, im, ft, nc in frames:
+                P.xg_preprocess(f.frame, gs, sid)
+                P.xg_bin_sort(f.frame, sid)
+                P.xg_render_fwd(f.frame, gs, im.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
+
+        per_view_pass()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(1, args.steps // 4)
+        e0.record(stream)
+        for _ in range(reps):
+            per_view_pass()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert all(f.status() == 0 for f, *_ in frames)
+        pv_ms = e0.elapsed_time(e1) / reps
+        out["per_view"] = {"ms_per_pass": pv_ms, "views_per_s": w.n_views / (pv_ms * 1e-3),
+                           "ms_per_view": pv_ms / w.n_views}
+        out["batched_over_per_view"] = out["views_per_s"] / out["per_view"]["views_per_s"]
+        del frames
+    del frame
+    torch.cuda.empty_cache()
+    return out
 
 
 def kernel_source_hash() -> str:
@@ -95,6 +198,10 @@ def main():
     from paper_2403_04116_amd import _lib as X
 
     dev = torch.device("cuda:0")
+    if args.only_acui:
+        st = P.settings(tile=args.tile, lds_batch=args.lds, persistent=bool(args.persistent))
+        print(json.dumps({"acui_forward": acui_forward(args, dev, torch.cuda.current_stream(), st)}))
+        return
     w = S.workload(args.workload)
     use_adam = (args.workload == 5) if args.adam < 0 else bool(args.adam)
     g_np = S.scene(args.workload)
@@ -360,6 +467,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    acui = None if args.no_acui else acui_forward(args, dev, stream, st)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of views ---------
     cpu = None
     if not args.no_cpu:
@@ -421,6 +530,7 @@ def main():
         "stages": stages,
         "rirf": rirf,
         "loss_eq11": loss_eq11,
+        "acui_forward": acui,
         "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
                  "revisited": upto},
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),

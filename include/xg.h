@@ -315,6 +315,20 @@ xg_status xg_adam_step(const xg_params *p /* [host] struct of device ptrs */,
                        int32_t *step, const xg_adam *c /* [host] */, float *scales, float *opacity,
                        float *intensity, const int32_t *gate, void *stream);
 
+/* ACUI initialisation of the Gaussian centres (Sec. 3.3, Eq. 13): a
+ * cuboid of size size[0] x size[1] x size[2] centred on the origin, divided
+ * into a grid[0] x grid[1] x grid[2] voxel grid, sampled at interval d:
+ * points (n1 S1 d / M1, n2 S2 d / M2, n3 S3 d / M3) for all integers
+ * |n_i| <= K_i = floor(M_i / (2 d)) + 1.  size, grid [host]; means [device]
+ * float32 [count][3], n1 slowest and n3 fastest, each n_i ascending; every
+ * coordinate is ((n S) d) / M evaluated in double and rounded once.
+ * xg_acui_count gives count = prod (2 K_i + 1) [host].  EINVAL: a size, d
+ * not finite and positive, a grid entry < 1, a count above INT32_MAX, null
+ * means or capacity (in points) below the count. */
+xg_status xg_acui_count(const double size[3], const int32_t grid[3], double d, int64_t *count);
+xg_status xg_acui_grid(const double size[3], const int32_t grid[3], double d, float *means,
+                       int64_t capacity, void *stream);
+
 /* Training objective of Eq. 11, L = (1 - gamma) L1 + gamma L_SSIM (the
  * paper's gamma is 0.2), and its gradient with respect to the rendered
  * images, for every view of the frame (image and target have the image

@@ -11,4 +11,5 @@ from ._lib import (XgCamera, XgError, XgFrame, XgGaussians, XgGrads, XgSettings,
                    xg_l1_grad, xg_layout_views, xg_preprocess, xg_preprocess_bwd, xg_render_bwd,
                    xg_render_counts, xg_render_fwd,
                    xg_workspace_size, xg_ws_layout_of)
-from .drr import DRRFunction, Frame, RIRFFunction, cameras, l1_grad, render, rirf, settings  # noqa: F401
+from .drr import (DRRFunction, Frame, RIRFFunction, acui_means, cameras, l1_grad, render,  # noqa: F401
+                  rirf, settings)

@@ -132,6 +132,11 @@ _L.xg_rirf_fwd.restype = _S
 _L.xg_rirf_fwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P]
 _L.xg_rirf_bwd.restype = _S
 _L.xg_rirf_bwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, _P]
+_L.xg_acui_count.restype = _S
+_L.xg_acui_count.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_double,
+                             C.POINTER(C.c_int64)]
+_L.xg_acui_grid.restype = _S
+_L.xg_acui_grid.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_double, _P, C.c_int64, _P]
 _L.xg_loss_grad.restype = _S
 _L.xg_loss_grad.argtypes = [C.POINTER(XgFrame), _P, _P, C.c_float, _P, _P, _P]
 _L.xg_l1_grad.restype = _S
@@ -145,7 +150,7 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
             "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
             "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd",
-            "xg_loss_grad")
+            "xg_loss_grad", "xg_acui_count", "xg_acui_grid")
 MAX_STORE_SLOTS = 4096
 
 
@@ -257,6 +262,20 @@ def xg_render_counts(frame: XgFrame, counts: int, stream: int = 0) -> None:
 def xg_l1_grad(image: int, target: int, dl_dimage: int, n_pixels: int, scale: float,
                stream: int = 0) -> None:
     _check(_L.xg_l1_grad(image, target, dl_dimage, n_pixels, scale, stream), "xg_l1_grad")
+
+
+def _acui_args(size, grid, d):
+    return (C.c_double * 3)(*map(float, size)), (C.c_int32 * 3)(*map(int, grid)), float(d)
+
+
+def xg_acui_count(size, grid, d: float) -> int:
+    out = C.c_int64(0)
+    _check(_L.xg_acui_count(*_acui_args(size, grid, d), C.byref(out)), "xg_acui_count")
+    return int(out.value)
+
+
+def xg_acui_grid(size, grid, d: float, means: int, capacity: int, stream: int = 0) -> None:
+    _check(_L.xg_acui_grid(*_acui_args(size, grid, d), means, capacity, stream), "xg_acui_grid")
 
 
 def xg_loss_grad(frame: XgFrame, image: int, target: int, gamma: float, dl_dimage: int,

@@ -9,6 +9,8 @@
 
 #include "common.h"
 
+#include <cmath>
+
 using namespace xg;
 
 namespace {
@@ -429,6 +431,44 @@ xg_status xg_render_counts(const xg_frame *f, int32_t *counts, void *stream) {
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
     return hip_status(launch_render_counts(ws, f->cams_dev, p, counts, (hipStream_t)stream));
+}
+
+// K_i = [M_i / (2 d)] + 1 and the point count; EINVAL unless every input is
+// finite and positive and the count fits a Gaussian count (int32).
+static xg_status acui_plan(const double size[3], const int32_t grid[3], double d, int32_t k[3],
+                           int64_t *count) {
+    if (!size || !grid || !(d > 0.0) || !std::isfinite(d)) return XG_EINVAL;
+    double total = 1.0;
+    for (int i = 0; i < 3; ++i) {
+        if (!(size[i] > 0.0) || !std::isfinite(size[i]) || grid[i] < 1) return XG_EINVAL;
+        const double h = std::floor((double)grid[i] / (2.0 * d)) + 1.0;
+        if (h > 1.0e6) return XG_EINVAL;
+        k[i] = (int32_t)h;
+        total *= 2.0 * h + 1.0;
+    }
+    if (total > (double)INT32_MAX) return XG_EINVAL;
+    *count = (int64_t)total;
+    return XG_OK;
+}
+
+xg_status xg_acui_count(const double size[3], const int32_t grid[3], double d, int64_t *count) {
+    int32_t k[3];
+    int64_t c = 0;
+    const xg_status st = acui_plan(size, grid, d, k, &c);
+    if (st != XG_OK) return st;
+    if (!count) return XG_EINVAL;
+    *count = c;
+    return XG_OK;
+}
+
+xg_status xg_acui_grid(const double size[3], const int32_t grid[3], double d, float *means,
+                       int64_t capacity, void *stream) {
+    int32_t k[3];
+    int64_t c = 0;
+    const xg_status st = acui_plan(size, grid, d, k, &c);
+    if (st != XG_OK) return st;
+    if (!means || capacity < c) return XG_EINVAL;
+    return hip_status(launch_acui_grid(size, grid, d, k, c, means, (hipStream_t)stream));
 }
 
 xg_status xg_loss_grad(const xg_frame *f, const float *image, const float *target, float gamma,

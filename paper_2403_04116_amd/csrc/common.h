@@ -173,6 +173,8 @@ hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Param
                                 int32_t *counts, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                                  const Params &p, const xg_grads &gr, hipStream_t s);
+hipError_t launch_acui_grid(const double size[3], const int32_t grid[3], double d, const int32_t k[3],
+                            int64_t count, float *means, hipStream_t s);
 int64_t loss_tiles(const xg_camera *cams_host, int n_views);
 hipError_t launch_loss_grad(const Ws &ws, const xg_camera *cams_dev, int64_t tiles,
                             const float *image, const float *target, float gamma, float *dl,

@@ -258,6 +258,15 @@ class Frame:
         return out
 
 
+def acui_means(size, grid, d: float, device="cuda", stream=None) -> torch.Tensor:
+    """ACUI Gaussian centres (Sec. 3.3, Eq. 13) generated on the GPU: a
+    float32 [count, 3] tensor, n1 slowest and n3 fastest."""
+    n = X.xg_acui_count(size, grid, d)
+    out = torch.empty((n, 3), dtype=torch.float32, device=device)
+    X.xg_acui_grid(size, grid, d, out.data_ptr(), n, _stream(stream))
+    return out
+
+
 def l1_grad(image: torch.Tensor, target: torch.Tensor, scale: float, out: torch.Tensor | None = None,
             stream=None) -> torch.Tensor:
     """dL/dI of the L1 term of Eq. 11: scale * sign(image - target)."""

@@ -19,6 +19,13 @@ Distributions, per Gaussian, drawn in this order from
 3. quaternions ~ N(0, I_4), normalised (w, x, y, z; scalar first)
 4. opacity     = logistic(N(0, 1))
 5. intensity   ~ U[0, 1]  (the activated view-independent intensity, Eq. 3)
+
+Workload 6 is the forward-only scan of the initialised model: centres on
+the ACUI grid (Sec. 3.3, Eq. 13; the grid itself is the method's, computed
+by the library or the oracle, so only its parameters live here) and the
+other attributes drawn as in 2-5 ("randomly initialised").  Its 100 views
+are evenly spaced over 0-180 degrees, like the paper's 100 projections per
+scene.
 """
 from __future__ import annotations
 
@@ -68,6 +75,13 @@ class Workload:
                 f"log-scale N(log {math.exp(self.log_scale_mean):.3g}, {self.log_scale_std})")
 
 
+# ACUI grid of workload 6: cuboid side 2 (the scanned cube [-1, 1]^3),
+# 256^3 voxels, sampling interval 8 voxels.
+ACUI_SIZE = (2.0, 2.0, 2.0)
+ACUI_GRID = (256, 256, 256)
+ACUI_D = 8.0
+
+
 def _seeds(c: int) -> dict:
     return {"scene": 1000 * c, "camera": 1000 * c + 1,
             "perturb": 1000 * c + 2, "upstream": 1000 * c + 3}
@@ -97,6 +111,12 @@ def workload(c: int) -> Workload:
         angles = rng.uniform(0.0, 2 * math.pi, size=16).tolist()
         return Workload(5, 1_000_000, [(512, 512)] * 16, angles,
                         math.log(0.01), 0.6, "l1_mean", adam=True, seeds=s)
+    if c == 6:
+        # n is the grid's point count, filled in by whoever builds the grid;
+        # scales around half the grid spacing 2 * 8 / 256
+        return Workload(6, 0, [(512, 512)] * 100, [math.pi * k / 100 for k in range(100)],
+                        math.log(0.03125), 0.3, "none", seeds=s,
+                        notes="ACUI grid (Eq. 13), forward only")
     raise ValueError(f"unknown workload {c}")
 
 
@@ -111,6 +131,23 @@ def gaussians(n: int, log_scale_mean: float, log_scale_std: float, seed: int) ->
     inten = rng.uniform(0.0, 1.0, size=n)
     return {
         "means": np.ascontiguousarray(means, dtype=np.float32),
+        "scales": np.ascontiguousarray(np.exp(log_scales), dtype=np.float32),
+        "quats": np.ascontiguousarray(quats, dtype=np.float32),
+        "opacity": np.ascontiguousarray(1.0 / (1.0 + np.exp(-logit)), dtype=np.float32),
+        "intensity": np.ascontiguousarray(inten, dtype=np.float32),
+    }
+
+
+def attributes(n: int, log_scale_mean: float, log_scale_std: float, seed: int) -> dict:
+    """Scales, quaternions, opacity and intensity of ``n`` Gaussians whose
+    centres come from elsewhere (the ACUI grid): draws 2-5 above, in order."""
+    rng = np.random.default_rng(seed)
+    log_scales = rng.normal(log_scale_mean, log_scale_std, size=(n, 3))
+    quats = rng.normal(0.0, 1.0, size=(n, 4))
+    quats /= np.linalg.norm(quats, axis=1, keepdims=True)
+    logit = rng.normal(0.0, 1.0, size=n)
+    inten = rng.uniform(0.0, 1.0, size=n)
+    return {
         "scales": np.ascontiguousarray(np.exp(log_scales), dtype=np.float32),
         "quats": np.ascontiguousarray(quats, dtype=np.float32),
         "opacity": np.ascontiguousarray(1.0 / (1.0 + np.exp(-logit)), dtype=np.float32),

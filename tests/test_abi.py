@@ -240,3 +240,29 @@ def test_invalid_feature_counts_rejected_before_any_hip_call():
         assert e.value.status == X.XG_EINVAL
     with pytest.raises(X.XgError):
         X.xg_rirf_fwd(0, fake, 10, 16, fake, 0)          # null features
+
+
+@pytest.mark.parametrize("size,grid,d", [((2, 2, 2), (256, 256, 256), 8.0),
+                                         ((3.0, 1.5, 0.75), (100, 60, 30), 3.5),
+                                         ((1, 1, 1), (4, 4, 4), 3.0),
+                                         ((2.0, 1.0, 0.5), (7, 9, 11), 1.0)])
+def test_acui_count_matches_oracle(size, grid, d):
+    from oracle import acui
+    assert X.xg_acui_count(size, grid, d) == acui.count(size, grid, d)
+
+
+def test_acui_validation():
+    """Bad ACUI parameters fail on the host, before any HIP call."""
+    good = ((2, 2, 2), (256, 256, 256), 8.0)
+    bad = [((0, 2, 2), (256, 256, 256), 8.0), ((2, float("inf"), 2), (256, 256, 256), 8.0),
+           ((2, 2, 2), (256, 0, 256), 8.0), ((2, 2, 2), (256, 256, 256), 0.0),
+           ((2, 2, 2), (256, 256, 256), float("nan")), ((2, 2, 2), (4096, 4096, 4096), 1.0)]
+    for size, grid, d in bad:
+        with pytest.raises(X.XgError) as e:
+            X.xg_acui_count(size, grid, d)
+        assert e.value.status == X.XG_EINVAL
+    n = X.xg_acui_count(*good)
+    for ptr, cap in ((0, n), (4096, n - 1)):
+        with pytest.raises(X.XgError) as e:
+            X.xg_acui_grid(*good, ptr, cap)
+        assert e.value.status == X.XG_EINVAL
