@@ -23,6 +23,9 @@ own ("loss_eq11").
 (Sec. 3.3, Eq. 13 grid of 35^3 centres, 100 views of 512 x 512 over 0-180
 degrees), batched and per view: the paper's inference measurement on a
 synthetic stand-in.  --no-acui skips it, --only-acui runs nothing else.
+"rgb_forward" compares the forward of the radiative model with that of the
+RGB model with spherical-harmonics colour (Eq. 2, degree 3) on the
+headline scene (Tab. 3a's comparison); --no-rgb skips it.
 """
 from __future__ import annotations
 
@@ -72,6 +75,8 @@ def parse():
                          "(0.8 L1 + 0.2 SSIM term, fused kernels)")
     ap.add_argument("--no-acui", action="store_true",
                     help="skip the forward-only scan of the ACUI-initialised model")
+    ap.add_argument("--no-rgb", action="store_true",
+                    help="skip the forward comparison with the RGB (spherical-harmonics) model")
     ap.add_argument("--only-acui", action="store_true",
                     help="run only the forward-only ACUI scan (prints its JSON object)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
@@ -168,6 +173,69 @@ def acui_forward(args, dev, stream, st) -> dict:
                            "ms_per_view": pv_ms / w.n_views}
         out["batched_over_per_view"] = out["views_per_s"] / out["per_view"]["views_per_s"]
         del frames
+    del frame
+    torch.cuda.empty_cache()
+    return out
+
+
+def rgb_forward(args, dev, stream, st, w, g, cams) -> dict:
+    """Forward of the radiative model against the comparison model (RGB
+    Gaussians with degree-3 spherical-harmonics colour, Eq. 2) on the same
+    scene and views: preprocess (+ colours), binning/sort, blend.  The
+    paper's Tab. 3a ratio (2.1x inference) is this comparison on trained
+    scenes."""
+    import numpy as np
+    import torch
+
+    import scenes as S
+    import paper_2403_04116_amd as P
+    from paper_2403_04116_amd import _lib as X
+
+    degree = 3
+    sh = torch.from_numpy(S.sh_coefficients(w.n, degree, w.seeds["scene"] + 7)).to(dev)
+    frame = P.Frame(w.n, cams, st, device=dev)
+    frame.fit_capacity(g)
+    sid = int(stream.cuda_stream)
+    gs = P.drr.gaussians_struct(g)
+    npx = frame.total_pixels
+    img1 = torch.empty(npx, device=dev)
+    img3 = torch.empty((3, npx), device=dev)
+    ft = torch.empty(npx, device=dev)
+    nc = torch.empty(npx, dtype=torch.int32, device=dev)
+    drr = [lambda: P.xg_preprocess(frame.frame, gs, sid),
+           lambda: P.xg_bin_sort(frame.frame, sid),
+           lambda: P.xg_render_fwd(frame.frame, gs, img1.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)]
+    rgb = [lambda: X.xg_preprocess_rgb(frame.frame, gs, sh.data_ptr(), degree, sid),
+           lambda: P.xg_bin_sort(frame.frame, sid),
+           lambda: X.xg_render_fwd_rgb(frame.frame, gs, img3.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)]
+
+    def run(calls):
+        for _ in range(args.warmup):
+            for c in calls:
+                c()
+        torch.cuda.synchronize()
+        rows = []
+        for _ in range(args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+            ev[0].record(stream)
+            for k, c in enumerate(calls):
+                c()
+                ev[k + 1].record(stream)
+            rows.append(ev)
+        torch.cuda.synchronize()
+        total = float(np.mean([r[0].elapsed_time(r[-1]) for r in rows]))
+        parts = [float(np.mean([r[k].elapsed_time(r[k + 1]) for r in rows])) for k in range(len(calls))]
+        return total, parts
+
+    d_ms, d_parts = run(drr)
+    r_ms, r_parts = run(rgb)
+    assert frame.status() == 0
+    names = ["preprocess", "bin_sort", "render_fwd"]
+    out = {"degree": degree, "views": w.n_views, "gaussians": w.n,
+           "radiative_ms": d_ms, "rgb_ms": r_ms, "rgb_over_radiative": r_ms / d_ms,
+           "radiative_views_per_s": w.n_views / (d_ms * 1e-3), "rgb_views_per_s": w.n_views / (r_ms * 1e-3),
+           "radiative_stages_ms": dict(zip(names, d_parts)), "rgb_stages_ms": dict(zip(names, r_parts)),
+           "paper_context": "Tab. 3a: 72 -> 148 fps (2.1x) from RGB to radiative, trained scenes"}
     del frame
     torch.cuda.empty_cache()
     return out
@@ -468,6 +536,7 @@ def main():
         del src, dst
 
     acui = None if args.no_acui else acui_forward(args, dev, stream, st)
+    rgb = None if args.no_rgb else rgb_forward(args, dev, stream, st, w, g, cams)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of views ---------
     cpu = None
@@ -531,6 +600,7 @@ def main():
         "rirf": rirf,
         "loss_eq11": loss_eq11,
         "acui_forward": acui,
+        "rgb_forward": rgb,
         "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
                  "revisited": upto},
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),

@@ -315,6 +315,26 @@ xg_status xg_adam_step(const xg_params *p /* [host] struct of device ptrs */,
                        int32_t *step, const xg_adam *c /* [host] */, float *scales, float *opacity,
                        float *intensity, const int32_t *gate, void *stream);
 
+/* Comparison model (the RGB Gaussians of 3D Gaussian splatting, Sec. 3.1
+ * Eq. 2, measured against the radiative model in Tab. 3a), forward only.
+ * xg_preprocess_rgb: xg_preprocess, then every (view, Gaussian)'s colour
+ * c = max(sum_{l <= degree} sum_{|m| <= l} k_l^m Y_l^m(d) + 1/2, 0) per
+ * channel, d the unit direction from the view's source (-R^T t) to the
+ * Gaussian centre, Y_l^m the real spherical harmonics with the
+ * Condon-Shortley phase; the colours live in the workspace until the next
+ * preprocess.  sh [device] float32 [n][(degree+1)^2][3], basis index
+ * l^2 + l + m, channel fastest; degree in 0..3.  g->intensity is not used
+ * by the RGB blend but must be a valid pointer.
+ * xg_render_fwd_rgb: Eq. 10 with the colour channels in place of the
+ * intensity, after xg_preprocess_rgb and xg_bin_sort; image [device] is
+ * planar float32 [3][total pixels], final_t and n_contrib as for
+ * xg_render_fwd.  EINVAL: as xg_preprocess / xg_render_fwd, null sh, degree
+ * outside 0..3, XG_F_PERSISTENT set (one workgroup per tile only). */
+xg_status xg_preprocess_rgb(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                            const float *sh, int32_t degree, void *stream);
+xg_status xg_render_fwd_rgb(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                            float *image, float *final_t, int32_t *n_contrib, void *stream);
+
 /* ACUI initialisation of the Gaussian centres (Sec. 3.3, Eq. 13): a
  * cuboid of size size[0] x size[1] x size[2] centred on the origin, divided
  * into a grid[0] x grid[1] x grid[2] voxel grid, sampled at interval d:

@@ -132,6 +132,10 @@ _L.xg_rirf_fwd.restype = _S
 _L.xg_rirf_fwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P]
 _L.xg_rirf_bwd.restype = _S
 _L.xg_rirf_bwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, _P]
+_L.xg_preprocess_rgb.restype = _S
+_L.xg_preprocess_rgb.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, C.c_int32, _P]
+_L.xg_render_fwd_rgb.restype = _S
+_L.xg_render_fwd_rgb.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P]
 _L.xg_acui_count.restype = _S
 _L.xg_acui_count.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_double,
                              C.POINTER(C.c_int64)]
@@ -150,7 +154,8 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_bin_sort", "xg_render_fwd", "xg_render_bwd", "xg_preprocess_bwd",
             "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
             "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd",
-            "xg_loss_grad", "xg_acui_count", "xg_acui_grid")
+            "xg_loss_grad", "xg_acui_count", "xg_acui_grid", "xg_preprocess_rgb",
+            "xg_render_fwd_rgb")
 MAX_STORE_SLOTS = 4096
 
 
@@ -262,6 +267,16 @@ def xg_render_counts(frame: XgFrame, counts: int, stream: int = 0) -> None:
 def xg_l1_grad(image: int, target: int, dl_dimage: int, n_pixels: int, scale: float,
                stream: int = 0) -> None:
     _check(_L.xg_l1_grad(image, target, dl_dimage, n_pixels, scale, stream), "xg_l1_grad")
+
+
+def xg_preprocess_rgb(frame: XgFrame, g: XgGaussians, sh: int, degree: int, stream: int = 0) -> None:
+    _check(_L.xg_preprocess_rgb(C.byref(frame), C.byref(g), sh, degree, stream), "xg_preprocess_rgb")
+
+
+def xg_render_fwd_rgb(frame: XgFrame, g: XgGaussians, image: int, final_t: int, n_contrib: int,
+                      stream: int = 0) -> None:
+    _check(_L.xg_render_fwd_rgb(C.byref(frame), C.byref(g), image, final_t, n_contrib, stream),
+           "xg_render_fwd_rgb")
 
 
 def _acui_args(size, grid, d):

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libxg.so")
-SOURCES = ["api.cpp", "preprocess.hip", "scan.hip", "sort.hip", "render.hip", "adam.hip", "loss.hip", "init.hip"]
+SOURCES = ["api.cpp", "preprocess.hip", "scan.hip", "sort.hip", "render.hip", "adam.hip", "loss.hip", "init.hip", "sh.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

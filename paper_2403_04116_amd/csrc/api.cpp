@@ -307,6 +307,33 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
     return hip_status(e);
 }
 
+xg_status xg_preprocess_rgb(const xg_frame *f, const xg_gaussians *g, const float *sh, int32_t degree,
+                            void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !sh || degree < 0 || degree > 3) return XG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    hipError_t e = launch_preprocess(ws, *g, f->cams_dev, p, s);
+    if (e == hipSuccess) e = launch_sh_color(ws, f->cams_dev, g->means, sh, degree, s);
+    return hip_status(e);
+}
+
+xg_status xg_render_fwd_rgb(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
+                            int32_t *n_contrib, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !image || !final_t || !n_contrib) return XG_EINVAL;
+    if (f->settings.flags & XG_F_PERSISTENT) return XG_EINVAL;
+    const Ws ws = resolve(f, P);
+    const Params p = params_of(f->settings);
+    return hip_status(launch_render_fwd_rgb(ws, f->cams_dev, p, image, final_t, n_contrib,
+                                            (hipStream_t)stream));
+}
+
 xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
                         int32_t *n_contrib, void *stream) {
     Plan P;

@@ -173,6 +173,10 @@ hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Param
                                 int32_t *counts, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
                                  const Params &p, const xg_grads &gr, hipStream_t s);
+hipError_t launch_sh_color(const Ws &ws, const xg_camera *cams_dev, const float *means, const float *sh,
+                           int degree, hipStream_t s);
+hipError_t launch_render_fwd_rgb(const Ws &ws, const xg_camera *cams, const Params &p, float *image,
+                                 float *final_t, int32_t *n_contrib, hipStream_t s);
 hipError_t launch_acui_grid(const double size[3], const int32_t grid[3], double d, const int32_t k[3],
                             int64_t count, float *means, hipStream_t s);
 int64_t loss_tiles(const xg_camera *cams_host, int n_views);

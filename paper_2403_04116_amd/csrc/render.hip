@@ -119,7 +119,7 @@ __device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, 
 template <int T, int NT, bool CULL>
 __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32_t b0, int cnt,
                                       const TileGeom &tg, float amin, float4 *s_a, float4 *s_b,
-                                      uint16_t *s_mask, uint32_t *s_rid) {
+                                      uint16_t *s_mask, uint32_t *s_rid, float4 *s_c = nullptr) {
     constexpr int SB = T / 8;
     for (int k = threadIdx.x; k < cnt; k += NT) {
         const uint32_t gi = vals[b0 + k];
@@ -152,6 +152,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         }
         s_mask[k] = (uint16_t)m;
         if (s_rid) s_rid[k] = (uint32_t)rid;
+        if (s_c) s_c[k] = rec.d;   // RGB colour of the view (comparison model)
     }
 }
 
@@ -172,12 +173,14 @@ __device__ __forceinline__ int wave_list(const uint16_t *s_mask, int cnt, int w,
     return n;
 }
 
-// LDS of one blending workgroup (the forward leaves rid and wmax unused).
-template <int T, int B>
+// LDS of one blending workgroup (the forward leaves rid and wmax unused;
+// c holds the staged RGB colours of the CH = 3 forward).
+template <int T, int B, int CH = 1>
 struct BlendLds {
     static constexpr int NW = T * T / kWave;
     float4 a[B];
     float4 b[B];
+    float4 c[CH == 3 ? B : 1];
     uint32_t rid[B];
     uint16_t mask[B];
     uint16_t list[NW][B];
@@ -185,11 +188,15 @@ struct BlendLds {
     int next;
 };
 
-template <int T, int B, bool COUNT, bool STORE>
+// CH = 1: the radiative intensity of the record (Eq. 10).  CH = 3: the
+// three colour channels of the record's fourth slot (the comparison model),
+// image planar [3][total pixels]; the blending decisions are the same.
+template <int T, int B, bool COUNT, bool STORE, int CH = 1>
 __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera *cams,
                                          const Params &p, float *image, float *final_t,
                                          int32_t *n_contrib, int32_t *counts, const TStore &ts,
-                                         BlendLds<T, B> &sh) {
+                                         BlendLds<T, B, CH> &sh) {
+    static_assert(CH == 1 || (CH == 3 && !COUNT && !STORE), "RGB forward: plain variant only");
     constexpr int NT = T * T;
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
@@ -213,7 +220,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     const float amin = p.alpha_min, amax = p.alpha_max, tmin = p.t_min;
     uint16_t *list = sh.list[w];
 
-    float Tr = 1.0f, C = 0.0f;
+    float Tr = 1.0f, C = 0.0f, Cg = 0.0f, Cb = 0.0f;
     int last = 0;
     int n_eval = 0, n_con = 0, n_upto = 0;
     bool done = !inside;
@@ -224,7 +231,8 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         if (!__syncthreads_or(!done)) break;
         // the counting variant keeps every rectangle evaluation (the work
         // count of the definition), the others skip sub-blocks out of reach
-        stage<T, NT, !COUNT>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr);
+        stage<T, NT, !COUNT>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr,
+                             CH == 3 ? sh.c : nullptr);
         __syncthreads();
         if (!__any(!done)) continue;
         const int nl = wave_list(s_mask, cnt, w, list);
@@ -246,7 +254,14 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 if (keep && nc < ts.slots) tbase[(int64_t)nc * NT] = Tr;
                 nc += keep ? 1 : 0;
             }
-            C = keep ? fmaf(sb.z * ev.alpha, Tr, C) : C;
+            if constexpr (CH == 3) {
+                const float4 sc = sh.c[k];
+                C = keep ? fmaf(sc.x * ev.alpha, Tr, C) : C;
+                Cg = keep ? fmaf(sc.y * ev.alpha, Tr, Cg) : Cg;
+                Cb = keep ? fmaf(sc.z * ev.alpha, Tr, Cb) : Cb;
+            } else {
+                C = keep ? fmaf(sb.z * ev.alpha, Tr, C) : C;
+            }
             Tr = keep ? Tn : Tr;
             last = keep ? (int)(b0 - s) + k + 1 : last;
             if (COUNT) {
@@ -267,6 +282,10 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             counts[2 * ws.total_pixels + o] = n_upto;
         } else {
             image[o] = C;
+            if constexpr (CH == 3) {
+                image[ws.total_pixels + o] = Cg;
+                image[2 * ws.total_pixels + o] = Cb;
+            }
             final_t[o] = Tr;
             n_contrib[o] = last;
         }
@@ -322,6 +341,17 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *ca
         fwd_tile<T, B, COUNT, false>(tile, ws, cams, p, image, final_t, n_contrib, counts, ts, sh);
     }
     finish_queue(&ws.hdr->queue_fwd, &ws.hdr->done_fwd);
+}
+
+// Forward of the comparison model: three colour channels per pixel, one
+// workgroup per tile.
+template <int T, int B>
+__global__ __launch_bounds__(T * T) void k_render_fwd_rgb(Ws ws, const xg_camera *cams, Params p,
+                                                          float *image, float *final_t,
+                                                          int32_t *n_contrib) {
+    __shared__ BlendLds<T, B, 3> sh;
+    fwd_tile<T, B, false, false, 3>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
+                                    final_t, n_contrib, nullptr, TStore{nullptr, nullptr, 0}, sh);
 }
 
 // DPP lane permutations (row = 16 lanes): quad xor 1, quad xor 2, lane
@@ -533,6 +563,15 @@ hipError_t fwd_t(const Ws &ws, const xg_camera *cams, const Params &p, float *im
 }
 
 template <int T, int B>
+hipError_t fwd_rgb_t(const Ws &ws, const xg_camera *cams, const Params &p, float *image,
+                     float *final_t, int32_t *n_contrib, hipStream_t st) {
+    const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
+    hipLaunchKernelGGL((k_render_fwd_rgb<T, B>), dim3(nb), dim3(T * T), 0, st, ws, cams, p, image,
+                       final_t, n_contrib);
+    return hipGetLastError();
+}
+
+template <int T, int B>
 hipError_t counts_t(const Ws &ws, const xg_camera *cams, const Params &p, int32_t *counts,
                     hipStream_t st) {
     const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
@@ -582,6 +621,11 @@ hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &
                              float *final_t, int32_t *n_contrib, int persistent, const TStore &ts,
                              hipStream_t s) {
     XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, persistent, ts, s)
+}
+
+hipError_t launch_render_fwd_rgb(const Ws &ws, const xg_camera *cams, const Params &p, float *image,
+                                 float *final_t, int32_t *n_contrib, hipStream_t s) {
+    XG_DISPATCH(fwd_rgb_t, ws, cams, p, image, final_t, n_contrib, s)
 }
 
 hipError_t launch_render_bwd(const Ws &ws, const xg_camera *cams, const Params &p,

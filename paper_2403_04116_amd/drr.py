@@ -184,6 +184,26 @@ class Frame:
                         n_contrib.data_ptr(), _stream(stream))
         return image, final_t, n_contrib
 
+    def forward_rgb(self, g: dict, sh: torch.Tensor, degree: int, out=None, stream=None):
+        """Forward of the comparison model (RGB Gaussians, SH colours of Eq. 2):
+        preprocess with colours, binning, three-channel blend.  Returns the
+        planar [3, total_pixels] image, final T and the last contributor."""
+        if sh.dtype != torch.float32 or not sh.is_contiguous() or \
+                sh.numel() != self.n * (degree + 1) ** 2 * 3:
+            raise ValueError("sh must be contiguous float32 [n, (degree+1)^2, 3]")
+        sid = _stream(stream)
+        gs = gaussians_struct(g)
+        if out is None:
+            out = (torch.empty((3, self.total_pixels), dtype=torch.float32, device=self.device),
+                   torch.empty(self.total_pixels, dtype=torch.float32, device=self.device),
+                   torch.empty(self.total_pixels, dtype=torch.int32, device=self.device))
+        image, final_t, n_contrib = out
+        X.xg_preprocess_rgb(self.frame, gs, sh.data_ptr(), degree, sid)
+        X.xg_bin_sort(self.frame, sid)
+        X.xg_render_fwd_rgb(self.frame, gs, image.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(),
+                            sid)
+        return image, final_t, n_contrib
+
     def forward(self, g: dict, out=None, stream=None):
         self.preprocess_sort(g, stream)
         return self.render_fwd(g, out, stream)

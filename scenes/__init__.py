@@ -155,6 +155,13 @@ def attributes(n: int, log_scale_mean: float, log_scale_std: float, seed: int) -
     }
 
 
+def sh_coefficients(n: int, degree: int, seed: int, std: float = 0.3) -> np.ndarray:
+    """Spherical-harmonics colour coefficients of the comparison model,
+    float32 [n, (degree + 1)^2, 3] ~ N(0, std^2)."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.normal(0.0, std, size=(n, (degree + 1) ** 2, 3)), dtype=np.float32)
+
+
 def perturb(g: dict, seed: int) -> dict:
     """A perturbed copy of a scene (the target scene for the L1 workloads)."""
     rng = np.random.default_rng(seed)

@@ -266,3 +266,23 @@ def test_acui_validation():
         with pytest.raises(X.XgError) as e:
             X.xg_acui_grid(*good, ptr, cap)
         assert e.value.status == X.XG_EINVAL
+
+
+def test_rgb_validation():
+    """The comparison model's entry points reject a null coefficient array, a
+    degree outside 0..3 and the persistent flag before any HIP call."""
+    f, _ = _frame()
+    need = P.xg_workspace_size(f)
+    f.cams_dev = 256
+    f.ws = 512
+    f.ws_bytes = need
+    g = X.XgGaussians(4096, 4096, 4096, 4096, 4096, 100)
+    for sh, deg in ((0, 3), (4096, -1), (4096, 4)):
+        with pytest.raises(X.XgError) as e:
+            X.xg_preprocess_rgb(f, g, sh, deg)
+        assert e.value.status == X.XG_EINVAL
+    fp, _ = _frame(flags=X.XG_F_PERSISTENT)
+    fp.cams_dev, fp.ws, fp.ws_bytes = 256, 512, P.xg_workspace_size(fp)
+    with pytest.raises(X.XgError) as e:
+        X.xg_render_fwd_rgb(fp, g, 4096, 4096, 4096)
+    assert e.value.status == X.XG_EINVAL
