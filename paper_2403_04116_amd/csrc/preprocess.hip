@@ -302,8 +302,8 @@ __global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_
 // no pairs), so every offset is below the capacity.
 //
 // The pairs of a workgroup's 256 consecutive items form one contiguous
-// range; when it fits, they are assembled in LDS and written as whole
-// lines, else each item writes its own.
+// range, assembled in LDS in windows of kEmitStage pairs and written as
+// whole lines.
 constexpr int kEmitStage = 2048;   // 16 KB of LDS: eight workgroups per CU
 
 __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int tile) {
@@ -328,13 +328,16 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
     __syncthreads();
     const uint32_t base = s_range[0];
     const uint32_t total = s_range[1] - base;
-    const bool staged = total <= (uint32_t)kEmitStage;
+    // this item's tile rectangle and the first tile of its view
+    int tx0 = 0, tx1 = -1, ty0 = 0, txn = 1, toff = 0;
+    uint32_t i = 0;
     if (cnt > 0) {
         const uint32_t idx = (uint32_t)val;
         const int v = (int)(idx / (uint32_t)ws.n);
-        const uint32_t i = idx - (uint32_t)v * (uint32_t)ws.n;
+        i = idx - (uint32_t)v * (uint32_t)ws.n;
         const xg_camera &c = cams[v];
-        const int txn = (c.width + tile - 1) / tile;
+        txn = (c.width + tile - 1) / tile;
+        toff = c.tile_offset;
         TileRect tr;
         if (!unpack_tile_rect((uint32_t)(val >> 32), tr)) {
             // rectangle too large to pack: read it from the record
@@ -344,35 +347,38 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
             tr.ty0 = (rc.w & 0xffff) / tile;
             tr.ty1 = (rc.w >> 16) / tile;
         }
-        const int tx0 = tr.tx0, tx1 = tr.tx1, ty0 = tr.ty0, ty1 = tr.ty1;
-        // at most cnt pairs (the slots the scan reserved), whatever the rectangle
-        if (staged) {
-            uint32_t *st = s_t + (off - base);
-            uint32_t *sv = s_v + (off - base);
-            uint32_t m = 0;
-            for (int ty = ty0; ty <= ty1 && m < cnt; ++ty)
-                for (int tx = tx0; tx <= tx1 && m < cnt; ++tx) {
-                    st[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
-                    sv[m] = i;
-                    ++m;
-                }
-        } else {
-            uint32_t *tt = ws.ptile[0] + off;
-            uint32_t *vv = ws.pval[0] + off;
-            uint32_t m = 0;
-            for (int ty = ty0; ty <= ty1 && m < cnt; ++ty)
-                for (int tx = tx0; tx <= tx1 && m < cnt; ++tx) {
-                    tt[m] = (uint32_t)(c.tile_offset + ty * txn + tx);
-                    vv[m] = i;
-                    ++m;
-                }
-        }
+        tx0 = tr.tx0;
+        tx1 = tr.tx1;
+        ty0 = tr.ty0;
     }
-    if (!staged) return;
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < total; k += blockDim.x) {
-        ws.ptile[0][base + k] = s_t[k];
-        ws.pval[0][base + k] = s_v[k];
+    const uint32_t rw = (uint32_t)(tx1 - tx0 + 1);
+    const uint32_t lo = off - base;   // this item's first pair, relative to the block's
+    // The block's pairs are one contiguous range; it is assembled in LDS in
+    // windows of kEmitStage pairs and written with whole lines.  An item
+    // writes the pairs of its range that fall in the window, at most cnt
+    // (the slots the scan reserved), row-major over its rectangle.
+    for (uint32_t w0 = 0; w0 < total; w0 += kEmitStage) {
+        const uint32_t w1 = min(total, w0 + (uint32_t)kEmitStage);
+        const uint32_t a = max(lo, w0), b = min(lo + cnt, w1);
+        if (cnt > 0 && a < b) {
+            const uint32_t m = a - lo;
+            int ty = ty0 + (int)(m / rw);
+            int tx = tx0 + (int)(m % rw);
+            for (uint32_t q = a; q < b; ++q) {
+                s_t[q - w0] = (uint32_t)(toff + ty * txn + tx);
+                s_v[q - w0] = i;
+                if (++tx > tx1) {
+                    tx = tx0;
+                    ++ty;
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < w1 - w0; k += blockDim.x) {
+            ws.ptile[0][base + w0 + k] = s_t[k];
+            ws.pval[0][base + w0 + k] = s_v[k];
+        }
+        __syncthreads();
     }
 }
 

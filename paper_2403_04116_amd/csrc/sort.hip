@@ -146,20 +146,24 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
     return peers;
 }
 
-// Digit histograms of every pass in one read of the keys: per-wavefront
-// LDS counters (plain LDS atomics), summed per workgroup into the global
-// bins.  A grid of a few workgroups per CU strides over the keys, so each
-// global bin receives few atomics.
+// Digit histograms of every pass in one read of the keys: LDS counters
+// (LDS atomics) summed per workgroup into the global bins.  Neighbouring
+// keys often share their high digits (the pairs of one item), so each bin
+// has kHistCopies interleaved copies and lane l counts into copy l mod
+// kHistCopies: lanes with equal digits then hit different banks instead
+// of serialising on one word.  A grid of a few workgroups per CU strides
+// over the keys, so each global bin receives few atomics.
+constexpr int kHistCopies = 8;
+
 template <class S>
 __global__ __launch_bounds__(S::kThreads) void k_sort_hist(Ws ws, int passes) {
     using Key = typename S::Key;
     constexpr int kSortThreads = S::kThreads, kSortItems = S::kItems;
     constexpr int kSortBlock = kSortThreads * kSortItems;
-    constexpr int NW = kSortThreads / kWave;
     const Ctl c = S::ctl(ws);
-    __shared__ uint32_t hist[NW][kMaxPasses][kRadix];
-    const int w = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < NW * kMaxPasses * kRadix; i += kSortThreads)
+    __shared__ uint32_t hist[kMaxPasses][kRadix][kHistCopies];
+    const int copy = lane_id() & (kHistCopies - 1);
+    for (int i = threadIdx.x; i < kMaxPasses * kRadix * kHistCopies; i += kSortThreads)
         (&hist[0][0][0])[i] = 0;
     __syncthreads();
     const Key *in = S::keys(ws, 0);
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(S::kThreads) void k_sort_hist(Ws ws, int passes) {
 #pragma unroll
             for (int k = 0; k < kSortItems; ++k) {
                 const int64_t j = base + (int64_t)k * kSortThreads + threadIdx.x;
-                if (j < c.n) atomicAdd(&hist[w][q][S::digit(key[k], c, q * kRadixBits)], 1u);
+                if (j < c.n) atomicAdd(&hist[q][S::digit(key[k], c, q * kRadixBits)][copy], 1u);
             }
         }
     }
@@ -185,7 +189,8 @@ __global__ __launch_bounds__(S::kThreads) void k_sort_hist(Ws ws, int passes) {
     for (int i = threadIdx.x; i < passes * kRadix; i += kSortThreads) {
         const int q = i / kRadix, d = i % kRadix;
         uint32_t h = 0;
-        for (int k = 0; k < NW; ++k) h += hist[k][q][d];
+#pragma unroll
+        for (int k = 0; k < kHistCopies; ++k) h += hist[q][d][k];
         if (h) atomicAdd(&ws.ghist[(q * kRadix + d) * kGhStride], h);
     }
 }
@@ -386,17 +391,41 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
 
 // ranges[2g], ranges[2g+1] = [start, end) of tile g in the sorted pairs
 // (the array is zero-filled first, so empty tiles read (0, 0)).
+// Each thread takes kRangeRun consecutive sorted keys (vector loads when
+// the run lies inside the pairs) plus the key before and after the run.
+constexpr int kRangeRun = 16;
+
 __global__ __launch_bounds__(256) void k_ranges(Ws ws) {
     const WsHeader *h = ws.hdr;
     const int64_t np = h->n_pairs;
     const int64_t n = (h->status != XG_OK || np > ws.cap) ? 0 : np;
     const uint32_t *tiles = ws.ptile[ws.pair_sel];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = tiles[i];
-        if (t >= (uint64_t)ws.total_tiles) continue;   // never, for pairs the emission wrote
-        if (i == 0 || tiles[i - 1] != t) ws.ranges[2 * (int64_t)t] = (uint32_t)i;
-        if (i == n - 1 || tiles[i + 1] != t) ws.ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeRun;
+    if (i0 >= n) return;
+    uint32_t t[kRangeRun + 2];
+    t[0] = i0 > 0 ? tiles[i0 - 1] : 0xffffffffu;
+    if (i0 + kRangeRun <= n) {
+        const uint4 *v = reinterpret_cast<const uint4 *>(tiles + i0);   // 64-byte aligned run
+#pragma unroll
+        for (int k = 0; k < kRangeRun / 4; ++k) {
+            const uint4 q = v[k];
+            t[1 + 4 * k] = q.x;
+            t[2 + 4 * k] = q.y;
+            t[3 + 4 * k] = q.z;
+            t[4 + 4 * k] = q.w;
+        }
+        t[kRangeRun + 1] = i0 + kRangeRun < n ? tiles[i0 + kRangeRun] : 0xffffffffu;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRangeRun + 1; ++k) t[1 + k] = i0 + k < n ? tiles[i0 + k] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int k = 0; k < kRangeRun; ++k) {
+        const int64_t i = i0 + k;
+        const uint32_t cur = t[1 + k];
+        if (i >= n || cur >= (uint32_t)ws.total_tiles) continue;   // never, for emitted pairs
+        if (t[k] != cur) ws.ranges[2 * (int64_t)cur] = (uint32_t)i;
+        if (t[k + 2] != cur) ws.ranges[2 * (int64_t)cur + 1] = (uint32_t)(i + 1);
     }
 }
 
@@ -472,8 +501,10 @@ hipError_t launch_ranges(const Ws &ws, bool cleared, hipStream_t s) {
         const hipError_t e = launch_fill_u32(ws.ranges, 0u, 2 * ws.total_tiles, s);
         if (e != hipSuccess) return e;
     }
-    int64_t nb = (ws.cap + 255) / 256;
-    if (nb > 16384) nb = 16384;
+    // one thread per run of kRangeRun keys of the capacity (the pair count is
+    // only known on the device)
+    const int64_t nb = (ws.cap + 256 * kRangeRun - 1) / (256 * kRangeRun);
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws);
     return hipGetLastError();
 }
