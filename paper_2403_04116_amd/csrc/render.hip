@@ -236,8 +236,14 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (!__any(!done)) continue;
         const int nl = wave_list(s_mask, cnt, w, list);
-        for (int j = 0; j < nl; ++j) {
-            const int k = (int)list[j];
+        // groups of 8 entries (the group bound is wavefront-uniform); the
+        // wavefront leaves the batch after a group once all its lanes have
+        // terminated
+        for (int j0 = 0; j0 < nl; j0 += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (j0 + u >= nl) break;
+            const int k = (int)list[j0 + u];
             const float4 sa = s_a[k];
             const float4 sb = s_b[k];
             const uint32_t rect = __float_as_uint(sb.w);
@@ -269,8 +275,8 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 n_con += keep ? 1 : 0;
                 n_upto = keep ? n_eval : n_upto;
             }
-            // leave the batch once every lane of the wavefront has terminated
-            if ((j & 7) == 7 && !__any(!done)) break;
+          }
+          if (!__any(!done)) break;
         }
     }
     if (STORE) ts.count[(int64_t)tile * NT + threadIdx.x] = nc;
