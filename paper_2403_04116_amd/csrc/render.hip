@@ -183,7 +183,7 @@ struct BlendLds {
     float4 c[CH == 3 ? B : 1];
     uint32_t rid[B];
     uint16_t mask[B];
-    uint16_t list[NW][B];
+    alignas(16) uint16_t list[NW][B];
     int wmax[NW];
     int next;
 };
@@ -197,6 +197,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                                          int32_t *n_contrib, int32_t *counts, const TStore &ts,
                                          BlendLds<T, B, CH> &sh) {
     static_assert(CH == 1 || (CH == 3 && !COUNT && !STORE), "RGB forward: plain variant only");
+    static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
     constexpr int NT = T * T;
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
@@ -236,14 +237,19 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (!__any(!done)) continue;
         const int nl = wave_list(s_mask, cnt, w, list);
+        int lk = -1;   // batch index of this lane's last contributor in the batch
         // groups of 8 entries (the group bound is wavefront-uniform); the
         // wavefront leaves the batch after a group once all its lanes have
         // terminated
         for (int j0 = 0; j0 < nl; j0 += 8) {
+          // the group's eight indices in one 16-byte read (in the row: j0 is
+          // a multiple of 8 and B of 8)
+          const uint4 idx8 = *reinterpret_cast<const uint4 *>(list + j0);
+          const uint32_t iw[4] = {idx8.x, idx8.y, idx8.z, idx8.w};
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             if (j0 + u >= nl) break;
-            const int k = (int)list[j0 + u];
+            const int k = (int)((iw[u >> 1] >> (16 * (u & 1))) & 0xffffu);
             const float4 sa = s_a[k];
             const float4 sb = s_b[k];
             const uint32_t rect = __float_as_uint(sb.w);
@@ -254,7 +260,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             const bool con = act && ev.alpha >= amin;
             const float Tn = Tr * (1.0f - ev.alpha);
             const bool term = con && Tn < tmin;
-            const bool keep = con && !term;
+            const bool keep = con != term;   // con and not term (term implies con)
             done = done || term;
             if (STORE) {
                 if (keep && nc < ts.slots) tbase[(int64_t)nc * NT] = Tr;
@@ -269,7 +275,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 C = keep ? fmaf(sb.z * ev.alpha, Tr, C) : C;
             }
             Tr = keep ? Tn : Tr;
-            last = keep ? (int)(b0 - s) + k + 1 : last;
+            lk = keep ? k : lk;
             if (COUNT) {
                 n_eval += act ? 1 : 0;
                 n_con += keep ? 1 : 0;
@@ -278,6 +284,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
           }
           if (!__any(!done)) break;
         }
+        if (lk >= 0) last = (int)(b0 - s) + lk + 1;
     }
     if (STORE) ts.count[(int64_t)tile * NT + threadIdx.x] = nc;
     if (inside) {
