@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--loss", choices=("l1", "eq11"), default="l1",
                     help="upstream gradient of the step: L1 alone, or the Eq. 11 objective "
                          "(0.8 L1 + 0.2 SSIM term, fused kernels)")
+    ap.add_argument("--fused", type=int, default=1,
+                    help="1: the L1 gradient in the forward blend's launch and gradients written by "
+                         "the projection adjoint (no clearing launch); 0: separate launches")
     ap.add_argument("--no-acui", action="store_true",
                     help="skip the forward-only scan of the ACUI-initialised model")
     ap.add_argument("--no-rgb", action="store_true",
@@ -313,8 +316,11 @@ def main():
     image, final_t, n_contrib = out
     # per-stage HIP events on the launch stream: marks[k] follows stage k
     loss_stage = "l1_grad" if args.loss == "l1" else "loss_grad"
-    STAGES = ["zero_grads", "preprocess", "bin_sort", "render_fwd", loss_stage, "render_bwd",
-              "preprocess_bwd"] + (["adam"] if opt is not None else [])
+    fuse_l1 = bool(args.fused) and args.loss == "l1" and store is None
+    write_grads = bool(args.fused)
+    STAGES = ([] if write_grads else ["zero_grads"]) + ["preprocess", "bin_sort"] \
+        + (["render_fwd_l1"] if fuse_l1 else ["render_fwd", loss_stage]) \
+        + ["render_bwd", "preprocess_bwd"] + (["adam"] if opt is not None else [])
     marks = []
 
     def mark(record, row):
@@ -326,26 +332,32 @@ def main():
     def step_batched(record: bool):
         row = []
         mark(record, row)
-        grads.zero_()
-        mark(record, row)
+        if not write_grads:
+            grads.zero_()
+            mark(record, row)
         P.xg_preprocess(frame.frame, gs, sid)
         mark(record, row)
         P.xg_bin_sort(frame.frame, sid)
         mark(record, row)
-        if store is None:
-            P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
-                            n_contrib.data_ptr(), sid)
+        if fuse_l1:
+            X.xg_render_fwd_l1(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
+                               n_contrib.data_ptr(), target.data_ptr(), scale, dl.data_ptr(), sid)
+            mark(record, row)
         else:
-            X.xg_render_fwd_store(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
-                                  n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
-                                  store.view.numel(), sid)
-        mark(record, row)
-        if args.loss == "l1":
-            P.xg_l1_grad(image.data_ptr(), target.data_ptr(), dl.data_ptr(), npx, scale, sid)
-        else:
-            X.xg_loss_grad(frame.frame, image.data_ptr(), target.data_ptr(), 0.2, dl.data_ptr(),
-                           loss_val.data_ptr(), sid)
-        mark(record, row)
+            if store is None:
+                P.xg_render_fwd(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
+                                n_contrib.data_ptr(), sid)
+            else:
+                X.xg_render_fwd_store(frame.frame, gs, image.data_ptr(), final_t.data_ptr(),
+                                      n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
+                                      store.view.numel(), sid)
+            mark(record, row)
+            if args.loss == "l1":
+                P.xg_l1_grad(image.data_ptr(), target.data_ptr(), dl.data_ptr(), npx, scale, sid)
+            else:
+                X.xg_loss_grad(frame.frame, image.data_ptr(), target.data_ptr(), 0.2, dl.data_ptr(),
+                               loss_val.data_ptr(), sid)
+            mark(record, row)
         if store is None:
             P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
         else:
@@ -353,7 +365,10 @@ def main():
                                   n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
                                   store.view.numel(), sid)
         mark(record, row)
-        P.xg_preprocess_bwd(frame.frame, gs, gr, sid)
+        if write_grads:
+            X.xg_preprocess_bwd_write(frame.frame, gs, gr, sid)
+        else:
+            P.xg_preprocess_bwd(frame.frame, gs, gr, sid)
         mark(record, row)
         if opt is not None:
             opt.step(grads, sid, gate=frame.status_ptr())
@@ -385,7 +400,8 @@ def main():
            if opt is not None else 0}
     stage_ms = {name: float(np.mean([row[k].elapsed_time(row[k + 1]) for row in marks]))
                 for k, name in enumerate(STAGES)}
-    fwd_ms, bwd_ms = stage_ms["render_fwd"], stage_ms["render_bwd"]
+    fwd_ms = stage_ms["render_fwd_l1"] if fuse_l1 else stage_ms["render_fwd"]
+    bwd_ms = stage_ms["render_bwd"]
 
     counts = frame.render_counts().double().sum(dim=1).cpu().numpy()
     evals, contribs, upto = (float(x) for x in counts)
@@ -410,6 +426,7 @@ def main():
         "bin_sort": ("hbm", n_items * (4 + 16 * item_passes + 8 + 12) + 16 * n_kept
                      + npairs * (8 + 4 + 16 * pair_passes + 4) + 8 * frame.total_tiles),
         "render_fwd": ("alu", fwd_flops),
+        "render_fwd_l1": ("alu", fwd_flops),   # plus 12 bytes per pixel for the L1 epilogue
         "l1_grad": ("hbm", 12 * npx),
         "loss_grad": ("hbm", LOSS_BYTES_PER_PX * npx),
         "render_bwd": ("alu", bwd_flops),
@@ -475,8 +492,13 @@ def main():
             for f, im, ft, nc, d, tg, n in frames:
                 P.xg_preprocess(f.frame, gs, sid)
                 P.xg_bin_sort(f.frame, sid)
-                P.xg_render_fwd(f.frame, gs, im.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
-                P.xg_l1_grad(im.data_ptr(), tg.data_ptr(), d.data_ptr(), n, scale, sid)
+                if args.fused:
+                    X.xg_render_fwd_l1(f.frame, gs, im.data_ptr(), ft.data_ptr(), nc.data_ptr(),
+                                       tg.data_ptr(), scale, d.data_ptr(), sid)
+                else:
+                    P.xg_render_fwd(f.frame, gs, im.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
+                    P.xg_l1_grad(im.data_ptr(), tg.data_ptr(), d.data_ptr(), n, scale, sid)
+                # the views' gradients add up: cleared once, accumulated per view
                 P.xg_render_bwd(f.frame, d.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
                 P.xg_preprocess_bwd(f.frame, gs, gr, sid)
 

@@ -201,6 +201,15 @@ xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
 xg_status xg_render_fwd(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                         float *image, float *final_t, int32_t *n_contrib, void *stream);
 
+/* xg_render_fwd followed by the L1 term of Eq. 11 in the same launch:
+ * also writes dl_dimage = scale * sign(image - target) (sign(0) = 0), equal
+ * bit for bit to xg_l1_grad on the image it writes; target and dl_dimage
+ * [device] have the image layout.  EINVAL: as xg_render_fwd, null target
+ * or dl_dimage, non-finite scale. */
+xg_status xg_render_fwd_l1(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                           float *image, float *final_t, int32_t *n_contrib, const float *target,
+                           float scale, float *dl_dimage, void *stream);
+
 /* Stage 4 (adjoint of Eq. 10): walks each pixel's list backwards from
  * n_contrib, recovering the transmittance by division instead of reading
  * stored per-contributor values, and accumulates per (view, Gaussian) the
@@ -239,6 +248,10 @@ xg_status xg_render_bwd_store(const xg_frame *f /* [host] */, const float *dl_di
  * atomics), and ACCUMULATES into `grads` (caller zeroes them). */
 xg_status xg_preprocess_bwd(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                             const xg_grads *grads /* [host] */, void *stream);
+/* The same adjoint, WRITING the gradients instead of adding to them (zeros
+ * for a Gaussian no view touched): the caller need not clear them first. */
+xg_status xg_preprocess_bwd_write(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                                  const xg_grads *grads /* [host] */, void *stream);
 
 /* Per-pixel work counts of the forward definition, for throughput
  * accounting and tests: counts[0][p] = evaluations (Gaussians of the list

@@ -132,6 +132,12 @@ _L.xg_rirf_fwd.restype = _S
 _L.xg_rirf_fwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P]
 _L.xg_rirf_bwd.restype = _S
 _L.xg_rirf_bwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, _P]
+_L.xg_render_fwd_l1.restype = _S
+_L.xg_render_fwd_l1.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P, C.c_float,
+                                _P, _P]
+_L.xg_preprocess_bwd_write.restype = _S
+_L.xg_preprocess_bwd_write.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), C.POINTER(XgGrads),
+                                       _P]
 _L.xg_preprocess_rgb.restype = _S
 _L.xg_preprocess_rgb.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, C.c_int32, _P]
 _L.xg_render_fwd_rgb.restype = _S
@@ -155,7 +161,7 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
             "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd",
             "xg_loss_grad", "xg_acui_count", "xg_acui_grid", "xg_preprocess_rgb",
-            "xg_render_fwd_rgb")
+            "xg_render_fwd_rgb", "xg_render_fwd_l1", "xg_preprocess_bwd_write")
 MAX_STORE_SLOTS = 4096
 
 
@@ -267,6 +273,17 @@ def xg_render_counts(frame: XgFrame, counts: int, stream: int = 0) -> None:
 def xg_l1_grad(image: int, target: int, dl_dimage: int, n_pixels: int, scale: float,
                stream: int = 0) -> None:
     _check(_L.xg_l1_grad(image, target, dl_dimage, n_pixels, scale, stream), "xg_l1_grad")
+
+
+def xg_render_fwd_l1(frame: XgFrame, g: XgGaussians, image: int, final_t: int, n_contrib: int,
+                     target: int, scale: float, dl_dimage: int, stream: int = 0) -> None:
+    _check(_L.xg_render_fwd_l1(C.byref(frame), C.byref(g), image, final_t, n_contrib, target, scale,
+                               dl_dimage, stream), "xg_render_fwd_l1")
+
+
+def xg_preprocess_bwd_write(frame: XgFrame, g: XgGaussians, grads: XgGrads, stream: int = 0) -> None:
+    _check(_L.xg_preprocess_bwd_write(C.byref(frame), C.byref(g), C.byref(grads), stream),
+           "xg_preprocess_bwd_write")
 
 
 def xg_preprocess_rgb(frame: XgFrame, g: XgGaussians, sh: int, degree: int, stream: int = 0) -> None:

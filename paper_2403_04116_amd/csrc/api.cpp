@@ -334,8 +334,9 @@ xg_status xg_render_fwd_rgb(const xg_frame *f, const xg_gaussians *g, float *ima
                                             (hipStream_t)stream));
 }
 
-xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
-                        int32_t *n_contrib, void *stream) {
+static xg_status render_fwd_common(const xg_frame *f, const xg_gaussians *g, float *image,
+                                   float *final_t, int32_t *n_contrib, const L1Fuse &l1,
+                                   void *stream) {
     Plan P;
     xg_status st = make_plan(f, true, P);
     if (st != XG_OK) return st;
@@ -349,7 +350,19 @@ xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, 
         if (e != hipSuccess) return hip_status(e);
     }
     return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib, persistent,
-                                        TStore{nullptr, nullptr, 0}, (hipStream_t)stream));
+                                        TStore{nullptr, nullptr, 0}, l1, (hipStream_t)stream));
+}
+
+xg_status xg_render_fwd(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
+                        int32_t *n_contrib, void *stream) {
+    return render_fwd_common(f, g, image, final_t, n_contrib, L1Fuse{nullptr, nullptr, 0.0f}, stream);
+}
+
+xg_status xg_render_fwd_l1(const xg_frame *f, const xg_gaussians *g, float *image, float *final_t,
+                           int32_t *n_contrib, const float *target, float scale, float *dl_dimage,
+                           void *stream) {
+    if (!target || !dl_dimage || !std::isfinite(scale)) return XG_EINVAL;
+    return render_fwd_common(f, g, image, final_t, n_contrib, L1Fuse{target, dl_dimage, scale}, stream);
 }
 
 xg_status xg_render_bwd(const xg_frame *f, const float *dl_dimage, const float *final_t,
@@ -416,7 +429,7 @@ xg_status xg_render_fwd_store(const xg_frame *f, const xg_gaussians *g, float *i
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
     return hip_status(launch_render_fwd(ws, f->cams_dev, p, image, final_t, n_contrib, 0, ts,
-                                        (hipStream_t)stream));
+                                        L1Fuse{nullptr, nullptr, 0.0f}, (hipStream_t)stream));
 }
 
 xg_status xg_render_bwd_store(const xg_frame *f, const float *dl_dimage, const float *final_t,
@@ -435,8 +448,8 @@ xg_status xg_render_bwd_store(const xg_frame *f, const float *dl_dimage, const f
                                         (hipStream_t)stream));
 }
 
-xg_status xg_preprocess_bwd(const xg_frame *f, const xg_gaussians *g, const xg_grads *grads,
-                            void *stream) {
+static xg_status preprocess_bwd_common(const xg_frame *f, const xg_gaussians *g,
+                                       const xg_grads *grads, bool accumulate, void *stream) {
     Plan P;
     xg_status st = make_plan(f, true, P);
     if (st != XG_OK) return st;
@@ -447,7 +460,18 @@ xg_status xg_preprocess_bwd(const xg_frame *f, const xg_gaussians *g, const xg_g
     if (f->n == 0) return XG_OK;
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
-    return hip_status(launch_preprocess_bwd(ws, *g, f->cams_dev, p, *grads, (hipStream_t)stream));
+    return hip_status(launch_preprocess_bwd(ws, *g, f->cams_dev, accumulate, p, *grads,
+                                            (hipStream_t)stream));
+}
+
+xg_status xg_preprocess_bwd(const xg_frame *f, const xg_gaussians *g, const xg_grads *grads,
+                            void *stream) {
+    return preprocess_bwd_common(f, g, grads, true, stream);
+}
+
+xg_status xg_preprocess_bwd_write(const xg_frame *f, const xg_gaussians *g, const xg_grads *grads,
+                                  void *stream) {
+    return preprocess_bwd_common(f, g, grads, false, stream);
 }
 
 xg_status xg_render_counts(const xg_frame *f, int32_t *counts, void *stream) {

@@ -162,16 +162,23 @@ struct TStore {
     int slots;
 };
 
+// Optional L1 epilogue of the forward blend: dl[o] = scale * sign(image[o] -
+// target[o]) (sign(0) = 0), written with the image (dl null: none).
+struct L1Fuse {
+    const float *target;
+    float *dl;
+    float scale;
+};
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              float *image, float *final_t, int32_t *n_contrib,
-                             int persistent, const TStore &ts, hipStream_t s);
+                             int persistent, const TStore &ts, const L1Fuse &l1, hipStream_t s);
 hipError_t launch_render_bwd(const Ws &ws, const xg_camera *cams, const Params &p,
                              const float *dl_dimage, const float *final_t,
                              const int32_t *n_contrib, int persistent, const TStore &ts,
                              hipStream_t s);
 hipError_t launch_render_counts(const Ws &ws, const xg_camera *cams, const Params &p,
                                 int32_t *counts, hipStream_t s);
-hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
+hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams, bool accumulate,
                                  const Params &p, const xg_grads &gr, hipStream_t s);
 hipError_t launch_sh_color(const Ws &ws, const xg_camera *cams_dev, const float *means, const float *sh,
                            int degree, hipStream_t s);

@@ -389,6 +389,9 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
 // With power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 and [[A, B], [B, C]] the
 // inverse 2-D covariance: dL/du = [[A, B], [B, C]] (sum g d),
 // dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy, dL/dC = -sum g dy^2 / 2.
+// ACCUM: add into the gradients; else write them (zeros for a Gaussian no
+// view touched).
+template <bool ACCUM>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
                                                         Params p, xg_grads gr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -488,16 +491,25 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
 #pragma unroll
         for (int a = 0; a < 3; ++a) gm[a] += r[a] * gtx + r[3 + a] * gty + r[6 + a] * gtz;
     }
-    if (!any) return;
+    if (ACCUM && !any) return;
     float *om = gr.means + 3 * (int64_t)i;
     float *os = gr.scales + 3 * (int64_t)i;
     float *oq = gr.quats + 4 * (int64_t)i;
+    if (ACCUM) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { om[a] += (float)gm[a]; os[a] += (float)gs[a]; }
+        for (int a = 0; a < 3; ++a) { om[a] += (float)gm[a]; os[a] += (float)gs[a]; }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) oq[a] += (float)gq[a];
-    gr.opacity[i] += (float)go;
-    gr.intensity[i] += (float)gi;
+        for (int a = 0; a < 4; ++a) oq[a] += (float)gq[a];
+        gr.opacity[i] += (float)go;
+        gr.intensity[i] += (float)gi;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { om[a] = (float)gm[a]; os[a] = (float)gs[a]; }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) oq[a] = (float)gq[a];
+        gr.opacity[i] = (float)go;
+        gr.intensity[i] = (float)gi;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_l1_grad(const float *img, const float *tgt, float *out,
@@ -546,11 +558,14 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams,
+hipError_t launch_preprocess_bwd(const Ws &ws, const xg_gaussians &g, const xg_camera *cams, bool accumulate,
                                  const Params &p, const xg_grads &gr, hipStream_t s) {
     // one thread per Gaussian, summing its views in registers
     const int nb = (ws.n + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, ws, g, cams, p, gr);
+    if (accumulate)
+        hipLaunchKernelGGL(k_preprocess_bwd<true>, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, ws, g, cams, p, gr);
+    else
+        hipLaunchKernelGGL(k_preprocess_bwd<false>, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, ws, g, cams, p, gr);
     return hipGetLastError();
 }
 

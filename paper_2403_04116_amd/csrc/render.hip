@@ -195,7 +195,7 @@ template <int T, int B, bool COUNT, bool STORE, int CH = 1>
 __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera *cams,
                                          const Params &p, float *image, float *final_t,
                                          int32_t *n_contrib, int32_t *counts, const TStore &ts,
-                                         BlendLds<T, B, CH> &sh) {
+                                         const L1Fuse &l1, BlendLds<T, B, CH> &sh) {
     static_assert(CH == 1 || (CH == 3 && !COUNT && !STORE), "RGB forward: plain variant only");
     static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
     constexpr int NT = T * T;
@@ -301,6 +301,10 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             }
             final_t[o] = Tr;
             n_contrib[o] = last;
+            if (l1.dl) {
+                const float d = C - l1.target[o];
+                l1.dl[o] = d > 0.0f ? l1.scale : (d < 0.0f ? -l1.scale : 0.0f);
+            }
         }
     }
 }
@@ -341,17 +345,17 @@ template <int T, int B, bool COUNT, bool PERSIST, bool STORE>
 __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *cams, Params p,
                                                       float *image, float *final_t,
                                                       int32_t *n_contrib, int32_t *counts,
-                                                      TStore ts) {
+                                                      TStore ts, L1Fuse l1) {
     __shared__ BlendLds<T, B> sh;
     if (!PERSIST) {
         fwd_tile<T, B, COUNT, STORE>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
-                                     final_t, n_contrib, counts, ts, sh);
+                                     final_t, n_contrib, counts, ts, l1, sh);
         return;
     }
     for (;;) {
         const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_fwd, sh);
         if (tile < 0) break;
-        fwd_tile<T, B, COUNT, false>(tile, ws, cams, p, image, final_t, n_contrib, counts, ts, sh);
+        fwd_tile<T, B, COUNT, false>(tile, ws, cams, p, image, final_t, n_contrib, counts, ts, l1, sh);
     }
     finish_queue(&ws.hdr->queue_fwd, &ws.hdr->done_fwd);
 }
@@ -364,7 +368,8 @@ __global__ __launch_bounds__(T * T) void k_render_fwd_rgb(Ws ws, const xg_camera
                                                           int32_t *n_contrib) {
     __shared__ BlendLds<T, B, 3> sh;
     fwd_tile<T, B, false, false, 3>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
-                                    final_t, n_contrib, nullptr, TStore{nullptr, nullptr, 0}, sh);
+                                    final_t, n_contrib, nullptr, TStore{nullptr, nullptr, 0},
+                                    L1Fuse{nullptr, nullptr, 0.0f}, sh);
 }
 
 // DPP lane permutations (row = 16 lanes): quad xor 1, quad xor 2, lane
@@ -557,20 +562,20 @@ unsigned resident_grid(K kernel, int threads, int64_t work) {
 
 template <int T, int B>
 hipError_t fwd_t(const Ws &ws, const xg_camera *cams, const Params &p, float *image, float *final_t,
-                 int32_t *n_contrib, int persistent, const TStore &ts, hipStream_t st) {
+                 int32_t *n_contrib, int persistent, const TStore &ts, const L1Fuse &l1, hipStream_t st) {
     const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
     if (ts.t) {
         if (persistent) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_render_fwd<T, B, false, false, true>), dim3(nb), dim3(T * T), 0, st, ws,
-                           cams, p, image, final_t, n_contrib, nullptr, ts);
+                           cams, p, image, final_t, n_contrib, nullptr, ts, l1);
     } else if (persistent) {
         const unsigned g = resident_grid(k_render_fwd<T, B, false, true, false>, T * T, ws.total_tiles);
         if (g == 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_render_fwd<T, B, false, true, false>), dim3(g), dim3(T * T), 0, st, ws,
-                           cams, p, image, final_t, n_contrib, nullptr, ts);
+                           cams, p, image, final_t, n_contrib, nullptr, ts, l1);
     } else {
         hipLaunchKernelGGL((k_render_fwd<T, B, false, false, false>), dim3(nb), dim3(T * T), 0, st, ws,
-                           cams, p, image, final_t, n_contrib, nullptr, ts);
+                           cams, p, image, final_t, n_contrib, nullptr, ts, l1);
     }
     return hipGetLastError();
 }
@@ -589,7 +594,8 @@ hipError_t counts_t(const Ws &ws, const xg_camera *cams, const Params &p, int32_
                     hipStream_t st) {
     const unsigned nb = (unsigned)(ws.total_tiles > 0 ? ws.total_tiles : 1);
     hipLaunchKernelGGL((k_render_fwd<T, B, true, false, false>), dim3(nb), dim3(T * T), 0, st, ws,
-                       cams, p, nullptr, nullptr, nullptr, counts, TStore{nullptr, nullptr, 0});
+                       cams, p, nullptr, nullptr, nullptr, counts, TStore{nullptr, nullptr, 0},
+                       L1Fuse{nullptr, nullptr, 0.0f});
     return hipGetLastError();
 }
 
@@ -632,8 +638,8 @@ hipError_t bwd_t(const Ws &ws, const xg_camera *cams, const Params &p, const flo
 
 hipError_t launch_render_fwd(const Ws &ws, const xg_camera *cams, const Params &p, float *image,
                              float *final_t, int32_t *n_contrib, int persistent, const TStore &ts,
-                             hipStream_t s) {
-    XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, persistent, ts, s)
+                             const L1Fuse &l1, hipStream_t s) {
+    XG_DISPATCH(fwd_t, ws, cams, p, image, final_t, n_contrib, persistent, ts, l1, s)
 }
 
 hipError_t launch_render_fwd_rgb(const Ws &ws, const xg_camera *cams, const Params &p, float *image,

@@ -2,8 +2,9 @@
 one HIP graph.
 
 The step is: preprocess (Eq. 7-9), per-tile depth-sorted lists (Sec. 3.2),
-forward blending (Eq. 10), the L1 upstream gradient (Eq. 11), reverse
-blending and the projection adjoint, optionally followed by the fused Adam
+forward blending (Eq. 10) with the L1 upstream gradient (Eq. 11) in the
+same launch, reverse blending and the projection adjoint (writing fresh
+gradients, so no clearing launch), optionally followed by the fused Adam
 update of the raw parameters.  Every stage is a libxg kernel launch on one
 stream with no allocation, memset or synchronisation, so the whole
 sequence is captured once (torch.cuda.CUDAGraph is a hipGraph on ROCm) and
@@ -46,24 +47,20 @@ class TrainStep:
         f = self.frame
         gs = gaussians_struct(self.g)
         gr = X.XgGrads(*(self.grads[k].data_ptr() for k in PARAMS))
-        if self.zero_grads:
-            if hasattr(self.grads, "flat"):
-                self.grads.zero_()
-            else:
-                for t in self.grads.values():
-                    t.zero_()
         X.xg_preprocess(f.frame, gs, s)
         X.xg_bin_sort(f.frame, s)
         st = self.store
         if st is None:
-            X.xg_render_fwd(f.frame, gs, self.image.data_ptr(), self.final_t.data_ptr(),
-                            self.n_contrib.data_ptr(), s)
+            # forward blend and the L1 gradient in one launch
+            X.xg_render_fwd_l1(f.frame, gs, self.image.data_ptr(), self.final_t.data_ptr(),
+                               self.n_contrib.data_ptr(), self.target.data_ptr(), self.scale,
+                               self.dl.data_ptr(), s)
         else:
             X.xg_render_fwd_store(f.frame, gs, self.image.data_ptr(), self.final_t.data_ptr(),
                                   self.n_contrib.data_ptr(), st.view.data_ptr(), st.slots,
                                   st.view.numel(), s)
-        X.xg_l1_grad(self.image.data_ptr(), self.target.data_ptr(), self.dl.data_ptr(),
-                     self.image.numel(), self.scale, s)
+            X.xg_l1_grad(self.image.data_ptr(), self.target.data_ptr(), self.dl.data_ptr(),
+                         self.image.numel(), self.scale, s)
         if st is None:
             X.xg_render_bwd(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
                             self.n_contrib.data_ptr(), s)
@@ -71,7 +68,10 @@ class TrainStep:
             X.xg_render_bwd_store(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
                                   self.n_contrib.data_ptr(), st.view.data_ptr(), st.slots,
                                   st.view.numel(), s)
-        X.xg_preprocess_bwd(f.frame, gs, gr, s)
+        if self.zero_grads:
+            X.xg_preprocess_bwd_write(f.frame, gs, gr, s)   # this step's gradients only
+        else:
+            X.xg_preprocess_bwd(f.frame, gs, gr, s)         # added to the caller's
         if optimize and self.optimizer is not None:
             self.optimizer.step(self.grads, s, gate=f.status_ptr())
         for fn in self.post:
