@@ -258,7 +258,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             const bool act = !done && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
             const bool con = act && ev.alpha >= amin;
-            const float Tn = Tr * (1.0f - ev.alpha);
+            const float Tn = fmaf(-Tr, ev.alpha, Tr);   // T (1 - alpha), one rounding
             const bool term = con && Tn < tmin;
             const bool keep = con != term;   // con and not term (term implies con)
             done = done || term;
@@ -469,7 +469,8 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     wmax = __builtin_amdgcn_readfirstlane(wmax);
 
     float R = 0.0f;   // intensity behind, seen from just after the current Gaussian
-    float *g2d = ws.grad2d;
+    // the gradient word this lane adds (lanes 8q, q < 7, add value q of an entry)
+    float *g2q = ws.grad2d + (lane >> 3);
     for (int end = bmax; end > 0; end -= B) {
         const int b0 = max(end - B, 0);
         const int cnt = end - b0;
@@ -478,15 +479,15 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (b0 >= wmax) continue;
         const int nl = wave_list(s_mask, min(cnt, wmax - b0), w, list);
+        const int lastk = last - b0 - 1;   // batch index of this lane's last contributor
         for (int j = nl - 1; j >= 0; --j) {
             const int k = (int)list[j];
             const float4 sa = s_a[k];
             const float4 sb = s_b[k];
-            const int pos1 = b0 + k + 1;
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            const bool inr = pos1 <= last && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const bool inr = k <= lastk && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
             const bool act = inr && ev.alpha >= amin;
             if (!__any(act)) continue;
@@ -524,7 +525,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             v[7] = 0.0f;
             const float x = wave_reduce8(v);
             const int q = lane >> 3;
-            if ((lane & 7) == 0 && q < 7) atomicAdd(&g2d[8 * (int64_t)s_rid[k] + q], x);
+            if ((lane & 7) == 0 && q < 7) atomicAdd(g2q + 8 * (int64_t)s_rid[k], x);
         }
     }
 }
