@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define XG_ABI_VERSION 2
+#define XG_ABI_VERSION 3
 
 typedef enum {
     XG_OK = 0,
@@ -109,11 +109,13 @@ typedef struct {
 } xg_frame;
 
 /* Workspace sub-buffer offsets (bytes from ws), for inspection and tests.
- * The sorted lists are stored as parallel arrays: pair p of the sorted
- * order has global tile id pair_tiles[p] and Gaussian index pair_values[p];
- * its sort key is (pair_tiles[p] << 32) | float32 bits of the camera depth
- * of (view of that tile, Gaussian pair_values[p]), which is word 7 of that
- * (view, Gaussian)'s 64-byte render record. */
+ * Pair p of the sorted order has a global tile id and a Gaussian index.
+ * When pair_index_bits = b > 0 they share one word: pair_tiles[p] =
+ * tile << b | index (tile bits + b <= 32; pair_values is the same array);
+ * when b = 0 they are parallel arrays pair_tiles[p], pair_values[p].  The
+ * pair's sort key is (tile << 32) | float32 bits of the camera depth of
+ * (view of that tile, that Gaussian), which is word 7 of that (view,
+ * Gaussian)'s 64-byte render record. */
 typedef struct {
     size_t status;      /* int32: XG_OK or XG_ECAPACITY                       */
     size_t n_pairs;     /* int32: pairs emitted (may exceed the capacity)     */
@@ -126,6 +128,7 @@ typedef struct {
     size_t ranges;      /* uint32[total_tiles][2]: [start, end) per tile      */
     size_t grad2d;      /* float[n_views*n][8]: per-view 2-D gradients        */
     size_t total;       /* bytes needed                                       */
+    size_t pair_index_bits; /* b above: index bits of a packed pair, 0 = two arrays */
 } xg_ws_layout;
 
 /* Returns XG_ABI_VERSION. */

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libxg.so")
 
 XG_OK, XG_EINVAL, XG_ECAPACITY, XG_EHIP = 0, 1, 2, 3
 XG_F_PERSISTENT = 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_FEATURES = 64
 
 
@@ -80,7 +80,7 @@ class XgFrame(C.Structure):
 class XgWsLayout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in (
         "status", "n_pairs", "depth_range", "records", "counts", "offsets", "pair_tiles",
-        "pair_values", "ranges", "grad2d", "total")]
+        "pair_values", "ranges", "grad2d", "total", "pair_index_bits")]
 
 
 if not os.path.exists(LIB_PATH):

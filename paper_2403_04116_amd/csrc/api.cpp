@@ -72,7 +72,7 @@ struct Plan {
     xg_ws_layout lay;
     size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, lookback[2], tile_order, ssim;
     int64_t total_px, total_tiles, n_items;
-    int32_t item_blocks, pair_blocks, tile_bits, pair_passes;
+    int32_t item_blocks, pair_blocks, tile_bits, pair_passes, pair_gbits;
 };
 
 int bits_of(int64_t v) { return v <= 0 ? 0 : 64 - __builtin_clzll((unsigned long long)v); }
@@ -84,9 +84,13 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     const int64_t cap = f->pair_capacity;
     P.n_items = ni;
     P.item_blocks = (int32_t)((ni + kItemSortBlock - 1) / kItemSortBlock);
-    P.pair_blocks = (int32_t)((cap + kPairSortBlock - 1) / kPairSortBlock);
     P.tile_bits = bits_of(P.total_tiles - 1);
     P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
+    // one word per pair when tile id and Gaussian index fit 32 bits together
+    const int gb = bits_of((int64_t)f->n - 1) > 0 ? bits_of((int64_t)f->n - 1) : 1;
+    P.pair_gbits = P.tile_bits + gb <= 32 ? gb : 0;
+    const int64_t pblock = P.pair_gbits ? kPackedSortBlock : kPairSortBlock;
+    P.pair_blocks = (int32_t)((cap + pblock - 1) / pblock);
     const int64_t lb_words = (int64_t)kRadix * (P.item_blocks > P.pair_blocks ? P.item_blocks : P.pair_blocks);
     const int64_t scan_words = (ni + kScanBlock - 1) / kScanBlock + 1;
     // depth partials: one pair per preprocess workgroup
@@ -106,7 +110,10 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     for (int b = 0; b < 2; ++b) { P.ikeys[b] = o; o = align_up(o + 4 * (size_t)ni); }
     for (int b = 0; b < 2; ++b) { P.ivals[b] = o; o = align_up(o + 8 * (size_t)ni); }
     for (int b = 0; b < 2; ++b) { P.ptile[b] = o; o = align_up(o + 4 * (size_t)cap); }
-    for (int b = 0; b < 2; ++b) { P.pval[b] = o; o = align_up(o + 4 * (size_t)cap); }
+    for (int b = 0; b < 2; ++b) {   // not needed for packed pairs
+        P.pval[b] = o;
+        if (P.pair_gbits == 0) o = align_up(o + 4 * (size_t)cap);
+    }
     P.ghist = o;              o = align_up(o + 4 * (size_t)kSortCtlWords);
     for (int b = 0; b < 2; ++b) { P.lookback[b] = o; o = align_up(o + 8 * (size_t)lb_words); }
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
@@ -114,7 +121,8 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
     P.ssim = o;               o = align_up(o + 12 * (size_t)P.total_px + 4 * (size_t)loss_tiles(f->cams, f->n_views));
     L.pair_tiles = P.ptile[P.pair_passes & 1];
-    L.pair_values = P.pval[P.pair_passes & 1];
+    L.pair_values = P.pair_gbits ? P.ptile[P.pair_passes & 1] : P.pval[P.pair_passes & 1];
+    L.pair_index_bits = (size_t)P.pair_gbits;
     L.total = o;
     if (need_ws && f->ws_bytes < L.total) return XG_EINVAL;
     return XG_OK;
@@ -154,6 +162,9 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.pair_blocks = P.pair_blocks;
     w.pair_passes = P.pair_passes;
     w.pair_sel = P.pair_passes & 1;
+    w.pair_gbits = P.pair_gbits;
+    w.pair_gmask = P.pair_gbits ? (uint32_t)((1ull << P.pair_gbits) - 1) : 0xffffffffu;
+    w.pair_vals = P.pair_gbits ? w.ptile[w.pair_sel] : w.pval[w.pair_sel];
     return w;
 }
 

@@ -89,6 +89,13 @@ struct Ws {
     int32_t pair_blocks;   // radix-sort blocks over the pair capacity
     int32_t pair_passes;   // 8-bit passes over the tile id
     int32_t pair_sel;      // buffer holding the tile-sorted pairs (pair_passes & 1)
+    // Packed pairs: when the tile id and the Gaussian index fit one word,
+    // ptile holds tile << pair_gbits | index and pval is not used
+    // (pair_gbits = 0: two arrays).  The blending kernels read the index as
+    // pair_vals[p] & pair_gmask.
+    int32_t pair_gbits;
+    uint32_t pair_gmask;
+    const uint32_t *pair_vals;
 };
 
 // Scalar constants of one rendering.
@@ -137,6 +144,9 @@ constexpr int kItemSortThreads = 512, kItemSortItems = 16;    // 8192 items
 constexpr int kPairSortThreads = 1024, kPairSortItems = 16;   // 16384 pairs
 constexpr int kItemSortBlock = kItemSortThreads * kItemSortItems;
 constexpr int kPairSortBlock = kPairSortThreads * kPairSortItems;
+// packed pairs move 4-byte keys only, so a partition holds more of them
+constexpr int kPackedSortThreads = 1024, kPackedSortItems = 16;
+constexpr int kPackedSortBlock = kPackedSortThreads * kPackedSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 4;                            // 32 depth bits, 8 at a time

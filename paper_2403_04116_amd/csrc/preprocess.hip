@@ -365,7 +365,9 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
             int ty = ty0 + (int)(m / rw);
             int tx = tx0 + (int)(m % rw);
             for (uint32_t q = a; q < b; ++q) {
-                s_t[q - w0] = (uint32_t)(toff + ty * txn + tx);
+                const uint32_t t = (uint32_t)(toff + ty * txn + tx);
+                // packed: one word (tile << gbits | index); else two arrays
+                s_t[q - w0] = ws.pair_gbits ? (t << ws.pair_gbits) | i : t;
                 s_v[q - w0] = i;
                 if (++tx > tx1) {
                     tx = tx0;
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < w1 - w0; k += blockDim.x) {
             ws.ptile[0][base + w0 + k] = s_t[k];
-            ws.pval[0][base + w0 + k] = s_v[k];
+            if (!ws.pair_gbits) ws.pval[0][base + w0 + k] = s_v[k];
         }
         __syncthreads();
     }

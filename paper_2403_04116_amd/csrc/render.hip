@@ -122,7 +122,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
                                       uint16_t *s_mask, uint32_t *s_rid, float4 *s_c = nullptr) {
     constexpr int SB = T / 8;
     for (int k = threadIdx.x; k < cnt; k += NT) {
-        const uint32_t gi = vals[b0 + k];
+        const uint32_t gi = vals[b0 + k] & ws.pair_gmask;   // Gaussian index (packed or not)
         const int64_t rid = (int64_t)tg.view * ws.n + gi;
         const Record &rec = ws.rec[rid];
         const float4 ra = rec.a;
@@ -217,7 +217,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
 
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
     const uint32_t e = ws.ranges[2 * (int64_t)tile + 1];
-    const uint32_t *vals = ws.pval[ws.pair_sel];
+    const uint32_t *vals = ws.pair_vals;
     const float amin = p.alpha_min, amax = p.alpha_max, tmin = p.t_min;
     uint16_t *list = sh.list[w];
 
@@ -436,7 +436,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     const float pyr = (float)(py - tg.ry) + 0.5f;
 
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
-    const uint32_t *vals = ws.pval[ws.pair_sel];
+    const uint32_t *vals = ws.pair_vals;
     const float amin = p.alpha_min, amax = p.alpha_max;
     uint16_t *list = sh.list[w];
 

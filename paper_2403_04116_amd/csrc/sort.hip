@@ -67,6 +67,7 @@ struct ItemSort {
     }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
     static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
+    static constexpr bool kHasVal = true;
     static constexpr bool kSkipConstant = true;
     // the last pass that moves data also writes the tile counts in sorted order
     static constexpr bool kGatherCounts = true;
@@ -101,10 +102,36 @@ struct PairSort {
     static __device__ __forceinline__ uint32_t count_of(const Ws &, Val) { return 0; }
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPairSortThreads, kItems = kPairSortItems;
+    static constexpr bool kHasVal = true;
     static constexpr bool kGatherCounts = false;
     // the tile ranges are cleared here, ahead of k_ranges
     static constexpr bool kClearRanges = true;
     // every pass runs, so the result buffer (pair_passes & 1) is known on the host
+    static constexpr bool kSkipConstant = false;
+    static __device__ __forceinline__ void done(const Ws &, int) {}
+};
+
+// Packed pairs (tile id << gbits | Gaussian index in one word): the same
+// sort on the tile bits above the index, with no value array.
+struct PackedPairSort {
+    using Key = uint32_t;
+    using Val = uint32_t;   // unused
+    static __device__ __forceinline__ Ctl ctl(const Ws &ws) {
+        Ctl c = PairSort::ctl(ws);
+        c.dbits = ws.pair_gbits;   // the index bits below the tile id
+        return c;
+    }
+    static __device__ __forceinline__ uint32_t digit(Key key, const Ctl &c, int shift) {
+        return (key >> (c.dbits + shift)) & (kRadix - 1);
+    }
+    static __device__ __forceinline__ Key *keys(const Ws &ws, int b) { return ws.ptile[b]; }
+    static __device__ __forceinline__ Val *vals(const Ws &, int) { return nullptr; }
+    static __device__ __forceinline__ uint32_t count_of(const Ws &, Val) { return 0; }
+    static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
+    static constexpr int kThreads = kPackedSortThreads, kItems = kPackedSortItems;
+    static constexpr bool kHasVal = false;
+    static constexpr bool kGatherCounts = false;
+    static constexpr bool kClearRanges = true;
     static constexpr bool kSkipConstant = false;
     static __device__ __forceinline__ void done(const Ws &, int) {}
 };
@@ -207,7 +234,7 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
 
     __shared__ Key skeys[kSortBlock];
     using Val = typename S::Val;
-    __shared__ Val svals[kSortBlock];
+    __shared__ Val svals[S::kHasVal ? kSortBlock : 1];
     __shared__ uint32_t whist[kSortThreads / kWave][kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t goff[kRadix];
@@ -270,7 +297,7 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
         const int64_t j = wbase + (int64_t)r * kWave + lane;
         const int64_t jc = j < c.n ? j : c.n - 1;
         key[r] = kin[jc];
-        val[r] = vin[jc];
+        if constexpr (S::kHasVal) val[r] = vin[jc];
     }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
@@ -366,7 +393,7 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
             const uint32_t d = S::digit(key[r], c, shift);
             const uint32_t pos = bstart[d] + whist[w][d] + rank[r];
             skeys[pos] = key[r];
-            svals[pos] = val[r];
+            if constexpr (S::kHasVal) svals[pos] = val[r];
         }
     }
     __syncthreads();
@@ -382,8 +409,10 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
             const uint32_t dst = goff[d] + (uint32_t)pos - bstart[d];
             if (dst < (uint64_t)c.n) {   // always true unless a look-back gave up
                 kout[dst] = kk;
-                vout[dst] = svals[pos];
-                if (S::kGatherCounts && last_run) ws.icounts[dst] = S::count_of(ws, svals[pos]);
+                if constexpr (S::kHasVal) {
+                    vout[dst] = svals[pos];
+                    if (S::kGatherCounts && last_run) ws.icounts[dst] = S::count_of(ws, svals[pos]);
+                }
             }
         }
     }
@@ -403,21 +432,22 @@ __global__ __launch_bounds__(256) void k_ranges(Ws ws) {
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeRun;
     if (i0 >= n) return;
     uint32_t t[kRangeRun + 2];
-    t[0] = i0 > 0 ? tiles[i0 - 1] : 0xffffffffu;
+    const int gb = ws.pair_gbits;   // packed pairs: the tile id sits above the index bits
+    t[0] = i0 > 0 ? tiles[i0 - 1] >> gb : 0xffffffffu;
     if (i0 + kRangeRun <= n) {
         const uint4 *v = reinterpret_cast<const uint4 *>(tiles + i0);   // 64-byte aligned run
 #pragma unroll
         for (int k = 0; k < kRangeRun / 4; ++k) {
             const uint4 q = v[k];
-            t[1 + 4 * k] = q.x;
-            t[2 + 4 * k] = q.y;
-            t[3 + 4 * k] = q.z;
-            t[4 + 4 * k] = q.w;
+            t[1 + 4 * k] = q.x >> gb;
+            t[2 + 4 * k] = q.y >> gb;
+            t[3 + 4 * k] = q.z >> gb;
+            t[4 + 4 * k] = q.w >> gb;
         }
-        t[kRangeRun + 1] = i0 + kRangeRun < n ? tiles[i0 + kRangeRun] : 0xffffffffu;
+        t[kRangeRun + 1] = i0 + kRangeRun < n ? tiles[i0 + kRangeRun] >> gb : 0xffffffffu;
     } else {
 #pragma unroll
-        for (int k = 0; k < kRangeRun + 1; ++k) t[1 + k] = i0 + k < n ? tiles[i0 + k] : 0xffffffffu;
+        for (int k = 0; k < kRangeRun + 1; ++k) t[1 + k] = i0 + k < n ? tiles[i0 + k] >> gb : 0xffffffffu;
     }
 #pragma unroll
     for (int k = 0; k < kRangeRun; ++k) {
@@ -488,6 +518,7 @@ hipError_t launch_sort_items(const Ws &ws, hipStream_t s) {
 
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s) {
     if (ws.pair_passes > kMaxPasses) return hipErrorInvalidValue;
+    if (ws.pair_gbits) return radix_passes<PackedPairSort>(ws, ws.pair_passes, ws.pair_blocks, s);
     return radix_passes<PairSort>(ws, ws.pair_passes, ws.pair_blocks, s);
 }
 

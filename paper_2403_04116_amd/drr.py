@@ -142,8 +142,14 @@ class Frame:
         p = self.n_pairs()
         if self.status() != X.XG_OK:
             p = 0
-        tiles = self.ws_tensor(self.layout.pair_tiles, torch.int32, p).long()
-        vals = self.ws_tensor(self.layout.pair_values, torch.int32, p)
+        b = int(self.layout.pair_index_bits)
+        raw = self.ws_tensor(self.layout.pair_tiles, torch.int32, p).long() & 0xFFFFFFFF
+        if b:   # packed: tile << b | Gaussian index in one word
+            tiles = raw >> b
+            vals = (raw & ((1 << b) - 1)).to(torch.int32)
+        else:
+            tiles = raw
+            vals = self.ws_tensor(self.layout.pair_values, torch.int32, p)
         ranges = self.ws_tensor(self.layout.ranges, torch.int32, 2 * self.total_tiles)
         toff = torch.tensor([c.tile_offset for c in self.cams], dtype=torch.int64, device=self.device)
         view = torch.searchsorted(toff, tiles, right=True) - 1

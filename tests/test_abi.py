@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_status_strings():
-    assert P.xg_abi_version() == 2
+    assert P.xg_abi_version() == 3
     for st in (0, 1, 2, 3):
         assert X.status_string(st).startswith("XG_")
 
@@ -110,7 +110,9 @@ def test_workspace_size_grows_with_capacity_and_views():
     f2, _ = _frame(cap=100000)
     f3, _ = _frame(cap=1000, views=((64, 64), (64, 64)))
     s1, s2, s3 = (P.xg_workspace_size(f) for f in (f1, f2, f3))
-    assert s2 > s1 + 8 * (100000 - 1000) * 2 - 1
+    # two buffers of 4 bytes per pair (packed tile | index), or 2 x 8 when unpacked
+    per_pair = 8 if P.xg_ws_layout_of(f1).pair_index_bits else 16
+    assert s2 > s1 + per_pair * (100000 - 1000) - 1
     assert s3 > s1
     lay = P.xg_ws_layout_of(f1)
     assert lay.total == s1
@@ -286,3 +288,15 @@ def test_rgb_validation():
     with pytest.raises(X.XgError) as e:
         X.xg_render_fwd_rgb(fp, g, 4096, 4096, 4096)
     assert e.value.status == X.XG_EINVAL
+
+
+def test_pair_packing_decision():
+    """Tile id and Gaussian index share one word exactly when they fit 32 bits."""
+    small, _ = _frame(n=100, views=((64, 64),))                 # 16 tiles, 7 index bits
+    lay = P.xg_ws_layout_of(small)
+    assert lay.pair_index_bits == 7 and lay.pair_values == lay.pair_tiles
+    big, _ = _frame(n=1 << 20, views=((4096, 4096),) * 16)     # 2^20 tiles + 20 index bits
+    lay = P.xg_ws_layout_of(big)
+    assert lay.pair_index_bits == 0 and lay.pair_values != lay.pair_tiles
+    one, _ = _frame(n=1, views=((64, 64),))
+    assert P.xg_ws_layout_of(one).pair_index_bits == 1
