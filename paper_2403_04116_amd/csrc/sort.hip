@@ -21,9 +21,10 @@
 // before it from their published words (decoupled look-back: a partition
 // waits only on ones that started before it, so it always finishes); it
 // then stages its keys digit-sorted in LDS and writes each digit's run
-// contiguously.  Item passes past the varying bits, or whose digit is the
-// same for every key, are skipped without moving data (the header records
-// which buffer holds the result), so launch sequences are data independent.
+// contiguously.  Item passes past the varying bits are skipped without
+// moving data (the header records which buffer holds the result), so launch
+// sequences are data independent.  When the tile id and the Gaussian index
+// fit one 32-bit word, the pairs are sorted as single packed keys.
 #include "common.h"
 
 namespace xg {
@@ -68,7 +69,11 @@ struct ItemSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
     static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
     static constexpr bool kHasVal = true;
-    static constexpr bool kSkipConstant = true;
+    // passes whose digit is the same for every key could be skipped, but
+    // after the compaction to the varying depth bits that is rare, and
+    // finding out costs every partition of every pass four block-wide
+    // reductions over the histograms
+    static constexpr bool kSkipConstant = false;
     // the last pass that moves data also writes the tile counts in sorted order
     static constexpr bool kGatherCounts = true;
     static constexpr bool kClearRanges = false;
