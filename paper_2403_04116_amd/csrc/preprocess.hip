@@ -190,6 +190,11 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
                                                             const xg_camera *cams, Params p,
                                                             uint32_t *depth_part) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // The workgroup's records (and 2-D gradient accumulators) form one
+    // contiguous range; they are staged in LDS (16-byte part k of record t
+    // at s_rec[k][t]: conflict-free) and written with whole cache lines.
+    __shared__ float4 s_rec[4][kPreThreads];
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
     uint32_t dmin = 0xffffffffu, dmax = 0u;
     if (idx < ws.n_items) {
         const int v = (int)(idx / ws.n);
@@ -221,11 +226,11 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
             fx_ = fmin(fmax(fx_, -1073741824.0), 1073741824.0);
             fy_ = fmin(fmax(fy_, -1073741824.0), 1073741824.0);
             uint32_t dbits = __float_as_uint(ko.tz);
-            Record &rec = ws.rec[idx];
-            rec.a = make_float4((float)(ux - fx_), (float)(uy - fy_), (float)qa, (float)qb);
-            rec.b = make_float4((float)qc, o, g.intensity[i], __uint_as_float(dbits));
-            rec.c = make_int4((int)fx_, (int)fy_, ko.xl | (ko.xh << 16), ko.yl | (ko.yh << 16));
-            rec.d = make_float4(0.f, 0.f, 0.f, 0.f);
+            ra = make_float4((float)(ux - fx_), (float)(uy - fy_), (float)qa, (float)qb);
+            rb = make_float4((float)qc, o, g.intensity[i], __uint_as_float(dbits));
+            const int4 ci = make_int4((int)fx_, (int)fy_, ko.xl | (ko.xh << 16), ko.yl | (ko.yh << 16));
+            rc = make_float4(__int_as_float(ci.x), __int_as_float(ci.y), __int_as_float(ci.z),
+                             __int_as_float(ci.w));
             const int T = p.tile;
             count = (uint32_t)((ko.xh / T - ko.xl / T + 1) * (ko.yh / T - ko.yl / T + 1));
             trect = pack_tile_rect(ko.xl / T, ko.xh / T, ko.yl / T, ko.yh / T);
@@ -236,10 +241,29 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
         ws.counts[idx] = count;
         ws.ikeys[0][idx] = key;
         ws.ivals[0][idx] = (uint64_t)idx | ((uint64_t)trect << 32);
-        // clear this (view, Gaussian)'s 2-D gradient accumulator for the backward
-        float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d) + 2 * idx;
-        g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        g2[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // records of culled items are written as zeros (never read)
+    s_rec[0][threadIdx.x] = ra;
+    s_rec[1][threadIdx.x] = rb;
+    s_rec[2][threadIdx.x] = rc;
+    s_rec[3][threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    {
+        const int64_t first = (int64_t)blockIdx.x * kPreThreads;
+        const int nrec = (int)min((int64_t)kPreThreads, ws.n_items - first);
+        float4 *out = reinterpret_cast<float4 *>(ws.rec + first);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int j = m * kPreThreads + threadIdx.x;   // float4 j of the range: record j/4, part j%4
+            if (j / 4 < nrec) out[j] = s_rec[j & 3][j >> 2];
+        }
+        // clear the 2-D gradient accumulators (32 bytes per item) for the backward
+        float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d) + 2 * first;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int j = m * kPreThreads + threadIdx.x;
+            if (j / 2 < nrec) g2[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     }
     // block min/max of the kept depths -> one partial per block
     for (int off = kWave / 2; off > 0; off >>= 1) {
