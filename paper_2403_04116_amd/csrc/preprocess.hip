@@ -169,11 +169,12 @@ __device__ __forceinline__ void project64(const float *m, const float *s, const 
     P.sxy = P.B[0] * P.B[3] + P.B[1] * P.B[4] + P.B[2] * P.B[5];
 }
 
-// The key path of one (view, Gaussian), kept out of line so its operation
-// sequence is compiled on its own.
-// (Returned by value: an out-parameter of an out-of-line call lives in
-// scratch memory.)
-__device__ __noinline__ KeyOut key_path(const float *m, const float *s, const float *q, float o,
+// The key path of one (view, Gaussian).  Its float32 operation sequence is
+// fixed by the contraction-off scope of key_gaussian / key_view (IEEE
+// operations are not reordered or fused without fast-math flags), so it is
+// inlined: an out-of-line call kept the rotation and the result on the
+// stack (48 bytes of scratch traffic per item each way).
+__device__ __forceinline__ KeyOut key_path(const float *m, const float *s, const float *q, float o,
                                         const xg_camera &c, const Params p) {
     float M[9];
     KeyOut out;
