@@ -17,11 +17,11 @@
 // ("onesweep") form: a workgroup takes the next partition (8192 items or
 // 16384 pairs) from an
 // atomic counter, ranks its keys stably with wavefront ballots, publishes
-// its per-digit counts, and reads the running prefix of the partitions
-// before it from their published words (decoupled look-back: a partition
-// waits only on ones that started before it, so it always finishes); it
-// then stages its keys digit-sorted in LDS and writes each digit's run
-// contiguously.  Item passes past the varying bits are skipped without
+// its per-digit counts, stages its keys digit-sorted in LDS, reads the
+// running prefix of the partitions before it from their published words
+// (decoupled look-back: a partition waits only on ones that started before
+// it, and those publish their counts without waiting, so it always
+// finishes) and writes each digit's run contiguously.  Item passes past the varying bits are skipped without
 // moving data (the header records which buffer holds the result), so launch
 // sequences are data independent.  When the tile id and the Gaussian index
 // fit one 32-bit word, the pairs are sorted as single packed keys.
@@ -317,89 +317,85 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
         rank[r] = old + (uint32_t)__popcll(peers & lt_mask);
     }
     __syncthreads();
-    {
-        // threads d < 256 each own digit d
-        const int d = threadIdx.x;
-        const bool dig = d < kRadix;
-        uint32_t acc = 0, excl = 0;
-        bool failed = false;
-        if (dig) {
+    // Threads d < 256 each own digit d.  They turn the per-wave counts into
+    // exclusive per-wave offsets and publish the partition's count of the
+    // digit at once; the keys are then staged digit-sorted in LDS (their
+    // registers free) before the look-back for the global offsets.
+    const int d = threadIdx.x;
+    const bool dig = d < kRadix;
+    uint32_t acc = 0;
+    uint64_t *lb = ws.lookback[pass & 1];
+    if (dig) {
 #pragma unroll
-            for (int k = 0; k < kSortThreads / kWave; ++k) {
-                const uint32_t t = whist[k][d];
-                whist[k][d] = acc;
-                acc += t;
-            }
-            uint64_t *lb = ws.lookback[pass & 1];
-            uint64_t *mine = lb + part * kRadix + d;
-            // publish this partition's count, then add up the predecessors'
-            if (part == 0) {
-                __hip_atomic_store(mine, kLbPrefix | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(mine, kLbAggregate | acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            // Look back over a window of kLookback predecessors at a time (their
-            // words are loaded together): add aggregates until a prefix; a
-            // predecessor that has not published yet is polled again.
-            uint32_t spins = 0;
-            for (int64_t q = part - 1; q >= 0;) {
-                uint64_t word[kLookback];
-#pragma unroll
-                for (int k = 0; k < kLookback; ++k)
-                    word[k] = (q - k >= 0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT)
-                                           : kLbPrefix;     // before partition 0: prefix 0
-                int used = 0;
-                bool stop = false, wait = false;
-#pragma unroll
-                for (int k = 0; k < kLookback; ++k) {
-                    if (stop || wait) continue;
-                    const uint64_t flag = word[k] & (3ull << 62);
-                    if (flag == 0) {
-                        wait = true;
-                    } else {
-                        excl += (uint32_t)word[k];
-                        ++used;
-                        stop = flag == kLbPrefix;
-                    }
-                }
-                if (stop) break;
-                q -= used;
-                if (wait) {
-                    if (++spins > kSpinLimit) {
-                        failed = true;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            if (part != 0)
-                __hip_atomic_store(mine, kLbPrefix | (uint32_t)(excl + acc), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            if (failed) __hip_atomic_store(&ws.hdr->status, (int32_t)XG_EHIP, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < kSortThreads / kWave; ++k) {
+            const uint32_t t = whist[k][d];
+            whist[k][d] = acc;
+            acc += t;
         }
-        // global start of digit d: keys with smaller digits, then this digit's
-        // keys in earlier partitions
-        uint32_t tot;
-        const uint32_t dstart = block_excl_scan(dig ? ws.ghist[(pass * kRadix + d) * kGhStride] : 0u,
-                                                scan_lds, &tot);
-        const uint32_t bs = block_excl_scan(acc, scan_lds, &tot);
-        if (dig) {
-            goff[d] = dstart + excl;
-            bstart[d] = bs;
-        }
+        __hip_atomic_store(lb + part * kRadix + d, (part == 0 ? kLbPrefix : kLbAggregate) | acc,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // global start of digit d (keys with smaller digits) and its start in
+    // this partition
+    uint32_t tot;
+    const uint32_t dstart = block_excl_scan(dig ? ws.ghist[(pass * kRadix + d) * kGhStride] : 0u,
+                                            scan_lds, &tot);
+    const uint32_t bs = block_excl_scan(acc, scan_lds, &tot);
+    if (dig) bstart[d] = bs;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t j = wbase + (int64_t)r * kWave + lane;
         if (j < c.n) {
-            const uint32_t d = S::digit(key[r], c, shift);
-            const uint32_t pos = bstart[d] + whist[w][d] + rank[r];
+            const uint32_t dr = S::digit(key[r], c, shift);
+            const uint32_t pos = bstart[dr] + whist[w][dr] + rank[r];
             skeys[pos] = key[r];
             if constexpr (S::kHasVal) svals[pos] = val[r];
         }
+    }
+    if (dig) {
+        // Look back over a window of kLookback predecessors at a time (their
+        // words are loaded together): add aggregates until a prefix; a
+        // predecessor that has not published yet is polled again.
+        uint32_t excl = 0, spins = 0;
+        bool failed = false;
+        for (int64_t q = part - 1; q >= 0;) {
+            uint64_t word[kLookback];
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k)
+                word[k] = (q - k >= 0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : kLbPrefix;     // before partition 0: prefix 0
+            int used = 0;
+            bool stop = false, wait = false;
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k) {
+                if (stop || wait) continue;
+                const uint64_t flag = word[k] & (3ull << 62);
+                if (flag == 0) {
+                    wait = true;
+                } else {
+                    excl += (uint32_t)word[k];
+                    ++used;
+                    stop = flag == kLbPrefix;
+                }
+            }
+            if (stop) break;
+            q -= used;
+            if (wait) {
+                if (++spins > kSpinLimit) {
+                    failed = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (part != 0)
+            __hip_atomic_store(lb + part * kRadix + d, kLbPrefix | (uint32_t)(excl + acc), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (failed) __hip_atomic_store(&ws.hdr->status, (int32_t)XG_EHIP, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        goff[d] = dstart + excl;
     }
     __syncthreads();
     const int64_t nvalid = min((int64_t)kSortBlock, c.n - base);
@@ -410,8 +406,8 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
         const int pos = k * kSortThreads + threadIdx.x;
         if (pos < nvalid) {
             const Key kk = skeys[pos];
-            const uint32_t d = S::digit(kk, c, shift);
-            const uint32_t dst = goff[d] + (uint32_t)pos - bstart[d];
+            const uint32_t dk = S::digit(kk, c, shift);
+            const uint32_t dst = goff[dk] + (uint32_t)pos - bstart[dk];
             if (dst < (uint64_t)c.n) {   // always true unless a look-back gave up
                 kout[dst] = kk;
                 if constexpr (S::kHasVal) {
