@@ -148,7 +148,7 @@ constexpr uint64_t kLbPrefix = 2ull << 62;      // inclusive prefix through this
 // to in a correct launch: predecessors publish before they wait); the sort
 // then reports XG_EHIP through the status word instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 20;
-constexpr int kLookback = 16;    // predecessors read per look-back step
+constexpr int kLookback = 4;     // predecessors read per look-back step
 
 // Zeroes the digit histograms, partition counters and the first pass's
 // look-back words of one sort.
