@@ -419,6 +419,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     constexpr int NT = T * T;
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
+    static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
     float4 *s_a = sh.a;
     float4 *s_b = sh.b;
     uint32_t *s_rid = sh.rid;
@@ -480,8 +481,16 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         if (b0 >= wmax) continue;
         const int nl = wave_list(s_mask, min(cnt, wmax - b0), w, list);
         const int lastk = last - b0 - 1;   // batch index of this lane's last contributor
-        for (int j = nl - 1; j >= 0; --j) {
-            const int k = (int)list[j];
+        // groups of 8 entries from the back, each group's indices in one
+        // 16-byte read (j0 is a multiple of 8 and B of 8, so the read stays in
+        // the row); entries past nl are skipped by a wavefront-uniform test
+        for (int j0 = (nl - 1) & ~7; j0 >= 0; j0 -= 8) {
+          const uint4 idx8 = *reinterpret_cast<const uint4 *>(list + j0);
+          const uint32_t iw[4] = {idx8.x, idx8.y, idx8.z, idx8.w};
+#pragma unroll
+          for (int u = 7; u >= 0; --u) {
+            if (j0 + u >= nl) continue;
+            const int k = (int)((iw[u >> 1] >> (16 * (u & 1))) & 0xffffu);
             const float4 sa = s_a[k];
             const float4 sb = s_b[k];
             const uint32_t rect = __float_as_uint(sb.w);
@@ -526,6 +535,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             const float x = wave_reduce8(v);
             const int q = lane >> 3;
             if ((lane & 7) == 0 && q < 7) atomicAdd(g2q + 8 * (int64_t)s_rid[k], x);
+          }
         }
     }
 }
