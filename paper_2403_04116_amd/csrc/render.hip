@@ -420,6 +420,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
     static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
+    static_assert((B & (B - 1)) == 0, "list indices are taken modulo B");
     float4 *s_a = sh.a;
     float4 *s_b = sh.b;
     uint32_t *s_rid = sh.rid;
@@ -487,12 +488,24 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         for (int j0 = (nl - 1) & ~7; j0 >= 0; j0 -= 8) {
           const uint4 idx8 = *reinterpret_cast<const uint4 *>(list + j0);
           const uint32_t iw[4] = {idx8.x, idx8.y, idx8.z, idx8.w};
+          // Each entry's record is loaded one entry ahead of its use.  Entries
+          // past nl are loaded too (and skipped): the index is taken modulo B,
+          // which keeps every valid entry (< B) and keeps whatever the row
+          // holds past nl (earlier batches, or LDS never written) in bounds.
+          int k_n = (int)((iw[3] >> 16) & (B - 1));
+          float4 sa_n = s_a[k_n];
+          float4 sb_n = s_b[k_n];
 #pragma unroll
           for (int u = 7; u >= 0; --u) {
+            const int k = k_n;
+            const float4 sa = sa_n;
+            const float4 sb = sb_n;
+            if (u > 0) {
+                k_n = (int)((iw[(u - 1) >> 1] >> (16 * ((u - 1) & 1))) & (B - 1));
+                sa_n = s_a[k_n];
+                sb_n = s_b[k_n];
+            }
             if (j0 + u >= nl) continue;
-            const int k = (int)((iw[u >> 1] >> (16 * (u & 1))) & 0xffffu);
-            const float4 sa = s_a[k];
-            const float4 sb = s_b[k];
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
