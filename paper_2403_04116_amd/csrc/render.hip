@@ -373,24 +373,30 @@ __global__ __launch_bounds__(T * T) void k_render_fwd_rgb(Ws ws, const xg_camera
 }
 
 // DPP lane permutations (row = 16 lanes): quad xor 1, quad xor 2, lane
-// i^8 within a row (rotate by 8), and mirror within each half row.
-#define XG_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
+// i^8 within a row (rotate by 8), and mirror within each half row.  Every
+// permutation reads a lane of the same row and all lanes are active, so the
+// bound control (a lane with no source reads 0) never applies; it spares
+// the compiler materialising the old value.
+#define XG_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, true))
 constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRowRor8 = 0x128;   // row_ror:8
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 
-// Sum of 8 per-lane values over the wavefront, transposed so that every
+// Sum of 7 per-lane values over the wavefront, transposed so that every
 // step halves the number of live values: afterwards the lanes whose bits
-// 0..2 are zero hold the total of value q = lane >> 3.  All steps are VALU
-// (gfx950 permlane swaps and DPP), no LDS traffic: 18 instructions.
-__device__ __forceinline__ float wave_reduce8(float v[8]) {
+// 0..2 are zero hold the total of value q = lane >> 3 for q < 7 (lanes
+// 56-63 hold a copy of value 3).  All steps are VALU (gfx950 permlane
+// swaps and DPP), no LDS traffic.
+__device__ __forceinline__ float wave_reduce7(float v[7]) {
     const int lane = lane_id();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         // lanes 0-31 end with value k summed over lane pairs (l, l+32),
-        // lanes 32-63 with value k+4
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 4]),
+        // lanes 32-63 with value k+4 (value 3 again for k = 3: the swap of a
+        // value with itself leaves its pair sums in both halves)
+        const float hi = k < 3 ? v[k + 4] : v[3];
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(hi),
                                                         false, false);
         v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
@@ -529,7 +535,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             const float ge = act ? g : 0.0f;
             const float it = sb.z;
             const float gT = ge * Tj;
-            float v[8];
+            float v[7];
             v[6] = gT * ev.alpha;                          // dL/d intensity
             const float galpha = gT * (it - R);            // dL/d alpha
             R = act ? fmaf(it, ev.alpha, om * R) : R;
@@ -544,8 +550,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             v[2] = v[0] * ev.dx;
             v[3] = v[0] * ev.dy;
             v[4] = v[1] * ev.dy;
-            v[7] = 0.0f;
-            const float x = wave_reduce8(v);
+            const float x = wave_reduce7(v);
             const int q = lane >> 3;
             if ((lane & 7) == 0 && q < 7) atomicAdd(g2q + 8 * (int64_t)s_rid[k], x);
           }
