@@ -158,7 +158,9 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
 
 // Compacts, in list order, the staged entries [0, cnt) whose rectangle
 // touches this wavefront's sub-block w into list[]; returns their number
-// (wavefront-uniform).
+// (wavefront-uniform).  An entry k is stored as 16 k, the byte offset of its
+// slot in the float4 record arrays (k < B <= 256, so 16 k fits 16 bits), and
+// the blend loops read records without scaling the index.
 __device__ __forceinline__ int wave_list(const uint16_t *s_mask, int cnt, int w, uint16_t *list) {
     const int lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -167,10 +169,15 @@ __device__ __forceinline__ int wave_list(const uint16_t *s_mask, int cnt, int w,
         const int k = c + lane;
         const bool sel = k < cnt && ((s_mask[k] >> w) & 1u);
         const uint64_t bal = __ballot(sel);
-        if (sel) list[n + __popcll(bal & lt)] = (uint16_t)k;
+        if (sel) list[n + __popcll(bal & lt)] = (uint16_t)(16 * k);
         n += __popcll(bal);
     }
     return n;
+}
+
+// Record slot at byte offset `off` (16 x its index) of a float4 array.
+__device__ __forceinline__ float4 slot16(const float4 *base, uint32_t off) {
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
 // LDS of one blending workgroup (the forward leaves rid and wmax unused;
@@ -237,7 +244,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (!__any(!done)) continue;
         const int nl = wave_list(s_mask, cnt, w, list);
-        int lk = -1;   // batch index of this lane's last contributor in the batch
+        int lk = -1;   // 16 x batch index of this lane's last contributor in the batch
         // groups of 8 entries (the group bound is wavefront-uniform); the
         // wavefront leaves the batch after a group once all its lanes have
         // terminated
@@ -249,9 +256,9 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             if (j0 + u >= nl) break;
-            const int k = (int)((iw[u >> 1] >> (16 * (u & 1))) & 0xffffu);
-            const float4 sa = s_a[k];
-            const float4 sb = s_b[k];
+            const uint32_t off = (iw[u >> 1] >> (16 * (u & 1))) & 0xffffu;   // 16 x batch index
+            const float4 sa = slot16(s_a, off);
+            const float4 sb = slot16(s_b, off);
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
@@ -267,7 +274,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 nc += keep ? 1 : 0;
             }
             if constexpr (CH == 3) {
-                const float4 sc = sh.c[k];
+                const float4 sc = slot16(sh.c, off);
                 C = keep ? fmaf(sc.x * ev.alpha, Tr, C) : C;
                 Cg = keep ? fmaf(sc.y * ev.alpha, Tr, Cg) : Cg;
                 Cb = keep ? fmaf(sc.z * ev.alpha, Tr, Cb) : Cb;
@@ -275,7 +282,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 C = keep ? fmaf(sb.z * ev.alpha, Tr, C) : C;
             }
             Tr = keep ? Tn : Tr;
-            lk = keep ? k : lk;
+            lk = keep ? (int)off : lk;
             if (COUNT) {
                 n_eval += act ? 1 : 0;
                 n_con += keep ? 1 : 0;
@@ -284,7 +291,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
           }
           if (!__any(!done)) break;
         }
-        if (lk >= 0) last = (int)(b0 - s) + lk + 1;
+        if (lk >= 0) last = (int)(b0 - s) + (lk >> 4) + 1;
     }
     if (STORE) ts.count[(int64_t)tile * NT + threadIdx.x] = nc;
     if (inside) {
@@ -426,7 +433,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
     static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
-    static_assert((B & (B - 1)) == 0, "list indices are taken modulo B");
+    static_assert((B & (B - 1)) == 0 && B <= 256, "list offsets are masked to 16 (B - 1) in 16 bits");
     float4 *s_a = sh.a;
     float4 *s_b = sh.b;
     uint32_t *s_rid = sh.rid;
@@ -487,7 +494,8 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         __syncthreads();
         if (b0 >= wmax) continue;
         const int nl = wave_list(s_mask, min(cnt, wmax - b0), w, list);
-        const int lastk = last - b0 - 1;   // batch index of this lane's last contributor
+        // 16 x batch index of this lane's last contributor (-16: none in the batch)
+        const int lastk16 = 16 * max(last - b0 - 1, -1);
         // groups of 8 entries from the back, each group's indices in one
         // 16-byte read (j0 is a multiple of 8 and B of 8, so the read stays in
         // the row); entries past nl are skipped by a wavefront-uniform test
@@ -495,27 +503,29 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
           const uint4 idx8 = *reinterpret_cast<const uint4 *>(list + j0);
           const uint32_t iw[4] = {idx8.x, idx8.y, idx8.z, idx8.w};
           // Each entry's record is loaded one entry ahead of its use.  Entries
-          // past nl are loaded too (and skipped): the index is taken modulo B,
-          // which keeps every valid entry (< B) and keeps whatever the row
-          // holds past nl (earlier batches, or LDS never written) in bounds.
-          int k_n = (int)((iw[3] >> 16) & (B - 1));
-          float4 sa_n = s_a[k_n];
-          float4 sb_n = s_b[k_n];
+          // past nl are loaded too (and skipped): the offset is masked to a
+          // multiple of 16 below 16 B, which keeps every valid entry and keeps
+          // whatever the row holds past nl (earlier batches, or LDS never
+          // written) inside the record arrays.
+          constexpr uint32_t kOffMask = 16u * (B - 1);
+          uint32_t off_n = (iw[3] >> 16) & kOffMask;
+          float4 sa_n = slot16(s_a, off_n);
+          float4 sb_n = slot16(s_b, off_n);
 #pragma unroll
           for (int u = 7; u >= 0; --u) {
-            const int k = k_n;
+            const uint32_t off = off_n;   // 16 x batch index
             const float4 sa = sa_n;
             const float4 sb = sb_n;
             if (u > 0) {
-                k_n = (int)((iw[(u - 1) >> 1] >> (16 * ((u - 1) & 1))) & (B - 1));
-                sa_n = s_a[k_n];
-                sb_n = s_b[k_n];
+                off_n = (iw[(u - 1) >> 1] >> (16 * ((u - 1) & 1))) & kOffMask;
+                sa_n = slot16(s_a, off_n);
+                sb_n = slot16(s_b, off_n);
             }
             if (j0 + u >= nl) continue;
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            const bool inr = k <= lastk && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const bool inr = (int)off <= lastk16 && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
             const bool act = inr && ev.alpha >= amin;
             if (!__any(act)) continue;
@@ -552,7 +562,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             v[4] = v[1] * ev.dy;
             const float x = wave_reduce7(v);
             const int q = lane >> 3;
-            if ((lane & 7) == 0 && q < 7) atomicAdd(g2q + 8 * (int64_t)s_rid[k], x);
+            if ((lane & 7) == 0 && q < 7) atomicAdd(g2q + 8 * (int64_t)s_rid[off >> 4], x);
           }
         }
     }
