@@ -1,6 +1,10 @@
-// Exclusive prefix sum of uint32 counts (reduce, scan of block sums,
-// downsweep).  Three launches, no inter-block waiting.  Used for the tile
-// counts of every (view, Gaussian) and for the radix-sort digit offsets.
+// Exclusive prefix sum of uint32 counts: block sums, then a downsweep that
+// adds the sums of the blocks before each block.  Up to kScanSelfBlocks
+// blocks, every downsweep block reduces those sums itself (two launches);
+// beyond that one block scans them first (three launches), since the
+// blocks' own reductions grow with the square of the block count.  No
+// inter-block waiting.  Used for the tile counts of the depth-sorted
+// (view, Gaussian) items.
 #include "common.h"
 
 namespace xg {
@@ -42,10 +46,19 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *sums, int64_t nb, i
     }
 }
 
+constexpr int64_t kScanSelfBlocks = 1024;
+
+// SELF: `sums` holds the raw block sums; each block adds those before it
+// (in 64 bits) and the last block writes the total and the capacity status.
+// Otherwise `sums` holds their exclusive scan (k_scan_top).
+template <bool SELF>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, uint32_t *out,
-                                                            int64_t n, const uint32_t *sums) {
+                                                            int64_t n, const uint32_t *sums,
+                                                            int32_t *total, int32_t *status,
+                                                            int64_t cap) {
     __shared__ uint32_t lds[kScanThreads / kWave + 1];
     __shared__ uint32_t tile[kScanBlock];
+    __shared__ uint64_t part[kScanThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
     // coalesced load into LDS, then each thread scans kScanItems consecutive
 #pragma unroll
@@ -53,7 +66,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, 
         const int64_t j = base + (int64_t)k * kScanThreads + threadIdx.x;
         tile[k * kScanThreads + threadIdx.x] = j < n ? in[j] : 0u;
     }
+    uint64_t before = 0;
+    if (SELF) {
+        uint64_t a = 0;
+        for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kScanThreads) a += sums[k];
+        for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+        if (lane_id() == 0) part[threadIdx.x / kWave] = a;
+    }
     __syncthreads();
+    if (SELF) {
+#pragma unroll
+        for (int w = 0; w < kScanThreads / kWave; ++w) before += part[w];
+    } else {
+        before = sums[blockIdx.x];
+    }
     uint32_t loc[kScanItems];
     uint32_t acc = 0;
 #pragma unroll
@@ -61,8 +87,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, 
         loc[k] = acc;
         acc += tile[threadIdx.x * kScanItems + k];
     }
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(acc, lds, &total) + sums[blockIdx.x];
+    uint32_t btotal;
+    const uint32_t ex = block_excl_scan(acc, lds, &btotal) + (uint32_t)before;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = ex + loc[k];
     __syncthreads();
@@ -70,6 +96,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, 
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t j = base + (int64_t)k * kScanThreads + threadIdx.x;
         if (j < n) out[j] = tile[k * kScanThreads + threadIdx.x];
+    }
+    if (SELF && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const uint64_t all = before + btotal;
+        if (total) *total = (int32_t)(all > 0x7fffffffull ? 0x7fffffff : all);
+        if (status && (int64_t)all > cap) *status = XG_ECAPACITY;
     }
 }
 
@@ -80,8 +111,14 @@ hipError_t launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *t
     const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     const unsigned g = (unsigned)(nb > 0 ? nb : 1);
     hipLaunchKernelGGL(k_scan_reduce, dim3(g), dim3(kScanThreads), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, (int64_t)g, total, status, cap);
-    hipLaunchKernelGGL(k_scan_down, dim3(g), dim3(kScanThreads), 0, s, in, out, n, tmp);
+    if ((int64_t)g <= kScanSelfBlocks) {
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(g), dim3(kScanThreads), 0, s, in, out, n, tmp, total,
+                           status, cap);
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, (int64_t)g, total, status, cap);
+        hipLaunchKernelGGL(k_scan_down<false>, dim3(g), dim3(kScanThreads), 0, s, in, out, n, tmp,
+                           nullptr, nullptr, cap);
+    }
     return hipGetLastError();
 }
 
