@@ -140,7 +140,7 @@ constexpr int kScanBlock = kScanThreads * kScanItems;   // 2048 elements
 
 // Radix-sort partitions (keys per workgroup = threads x keys per thread);
 // larger partitions shorten the look-back chains, these sizes measured best.
-constexpr int kItemSortThreads = 512, kItemSortItems = 16;    // 8192 items
+constexpr int kItemSortThreads = 1024, kItemSortItems = 8;    // 8192 items
 constexpr int kPairSortThreads = 1024, kPairSortItems = 16;   // 16384 pairs
 constexpr int kItemSortBlock = kItemSortThreads * kItemSortItems;
 constexpr int kPairSortBlock = kPairSortThreads * kPairSortItems;
