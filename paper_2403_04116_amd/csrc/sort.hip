@@ -183,8 +183,8 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // keys often share their high digits (the pairs of one item), so each bin
 // has kHistCopies interleaved copies and lane l counts into copy l mod
 // kHistCopies: lanes with equal digits then hit different banks instead
-// of serialising on one word.  A grid of a few workgroups per CU strides
-// over the keys, so each global bin receives few atomics.
+// of serialising on one word.  A grid of at most one workgroup per CU
+// strides over the keys, so each global bin receives few atomics.
 constexpr int kHistCopies = 8;
 
 template <class S>
@@ -497,7 +497,7 @@ hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s) {
     unsigned np = (unsigned)(((int64_t)blocks * kRadix + 255) / 256);
     if (np > 2048) np = 2048;
     hipLaunchKernelGGL(k_sort_prep<S>, dim3(np > 0 ? np : 1), dim3(256), 0, s, ws);
-    const unsigned nh = nb < 512 ? nb : 512;
+    const unsigned nh = nb < 256 ? nb : 256;
     hipLaunchKernelGGL(k_sort_hist<S>, dim3(nh), dim3(S::kThreads), 0, s, ws, passes);
     for (int p = 0; p < passes; ++p)
         hipLaunchKernelGGL(k_onesweep<S>, dim3(nb), dim3(S::kThreads), 0, s, ws, p, passes);
