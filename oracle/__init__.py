@@ -27,7 +27,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-ABI = 3
+ABI = 4
 
 FLAG_ALPHA_MIN = 1
 FLAG_T_MIN = 2
@@ -110,11 +110,13 @@ def lib():
         L.orc_sort_pairs.argtypes = [C.c_int64, P, P]
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int64, P]
         L.orc_render_brute.argtypes = [C.c_int32, P, P, P, P, P, C.POINTER(Cam), C.POINTER(Set),
-                                       C.c_int64, P, P, P, P, P, P]
+                                       C.c_int64, P, P, P, P, P, P, P]
         L.orc_render_binned.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32, C.POINTER(Cam),
-                                        C.POINTER(Set), P, P, P, P, P, P, P]
+                                        C.POINTER(Set), P, P, P, P, P, P, P, P, P]
         L.orc_backward.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32, C.POINTER(Cam),
-                                   C.POINTER(Set), P, C.c_int32, P, P, P, P, P, P, P, P, P]
+                                   C.POINTER(Set), P, C.c_int32, P, P, P, P, P, P, P, P, P, P]
+        L.orc_block_contributors.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32, C.POINTER(Cam),
+                                             C.POINTER(Set), P, P, P]
         _lib = L
     return _lib
 
@@ -196,8 +198,14 @@ def pairs(g: dict, cams, st: Settings, sort: bool = True) -> dict:
             "n_tiles": nt}
 
 
-def render_brute(g: dict, cam: Cam, st: Settings, pix=None) -> dict:
-    """Eq. 10 by brute force for pixels ``pix`` (flat y*W+x) of one view."""
+def _u8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def render_brute(g: dict, cam: Cam, st: Settings, pix=None, flip=None) -> dict:
+    """Eq. 10 by brute force for pixels ``pix`` (flat y*W+x) of one view.
+    ``flip`` (per selected pixel): render the other branch of the pixel's
+    first flagged decision."""
     g = _g64(g)
     n = g["means"].shape[0]
     if pix is None:
@@ -211,13 +219,17 @@ def render_brute(g: dict, cam: Cam, st: Settings, pix=None) -> dict:
     fl = np.zeros(m, dtype=np.int32)
     s = st.c()
     lib().orc_render_brute(n, _p(g["means"]), _p(g["scales"]), _p(g["quats"]), _p(g["opacity"]),
-                           _p(g["intensity"]), C.byref(cam), C.byref(s), m, _p(pix), _p(img),
-                           _p(tf), _p(last), _p(ev), _p(fl))
+                           _p(g["intensity"]), C.byref(cam), C.byref(s), m, _p(pix),
+                           _p(_u8(flip)), _p(img), _p(tf), _p(last), _p(ev), _p(fl))
     return {"image": img, "final_t": tf, "last": last, "evals": ev, "flags": fl}
 
 
-def render_binned(g: dict, cams, st: Settings, values, ranges) -> dict:
-    """Eq. 10 over the per-tile sorted lists, all pixels of all views (concatenated)."""
+def render_binned(g: dict, cams, st: Settings, values, ranges, flip=None, only=None) -> dict:
+    """Eq. 10 over the per-tile sorted lists, all pixels of all views (concatenated).
+
+    ``flip`` (per pixel, nullable): take the other branch of the pixel's
+    first flagged decision.  ``only`` (per pixel, nullable): render just
+    these pixels (the others read as zero)."""
     g = _g64(g)
     n = g["means"].shape[0]
     npx = int(sum(c.width * c.height for c in cams))
@@ -231,17 +243,42 @@ def render_binned(g: dict, cams, st: Settings, values, ranges) -> dict:
     s = st.c()
     lib().orc_render_binned(n, _p(g["means"]), _p(g["scales"]), _p(g["quats"]),
                             _p(g["opacity"]), _p(g["intensity"]), len(cams), cam_array(cams),
-                            C.byref(s), _p(values), _p(ranges), _p(img), _p(tf), _p(nc), _p(ev),
-                            _p(fl))
+                            C.byref(s), _p(values), _p(ranges), _p(_u8(flip)), _p(_u8(only)),
+                            _p(img), _p(tf), _p(nc), _p(ev), _p(fl))
     return {"image": img, "final_t": tf, "n_contrib": nc, "evals": ev, "flags": fl}
 
 
-def backward(g: dict, cams, st: Settings, dl_di, binned=None, sel=None, want_2d=False) -> dict:
+def block_contributors(g: dict, cams, st: Settings, values, ranges) -> np.ndarray:
+    """Per 8 x 8 pixel block (8-aligned in each view): the number of distinct
+    Gaussians contributing to at least one of its pixels, stored at the
+    block's first pixel of the concatenated image layout (0 elsewhere)."""
+    g = _g64(g)
+    n = g["means"].shape[0]
+    npx = int(sum(c.width * c.height for c in cams))
+    out = np.zeros(npx, dtype=np.int32)
+    values = np.ascontiguousarray(values, dtype=np.uint32)
+    ranges = np.ascontiguousarray(ranges, dtype=np.uint32)
+    s = st.c()
+    lib().orc_block_contributors(n, _p(g["means"]), _p(g["scales"]), _p(g["quats"]),
+                                 _p(g["opacity"]), _p(g["intensity"]), len(cams), cam_array(cams),
+                                 C.byref(s), _p(values), _p(ranges), _p(out))
+    return out
+
+
+def n_flags(flags) -> np.ndarray:
+    """Number of flagged decisions per pixel (decisions within a relative
+    margin of a threshold)."""
+    return np.asarray(flags) >> 8
+
+
+def backward(g: dict, cams, st: Settings, dl_di, binned=None, sel=None, want_2d=False,
+             flip=None) -> dict:
     """Adjoint of Eq. 10 and Eq. 7-9 for upstream gradient ``dl_di`` (concatenated views).
 
     ``binned`` = (values, ranges) to traverse tile lists, else brute force.
     ``sel`` = boolean mask of Gaussians whose gradients must be exact (only
-    pixels inside their rectangles are processed).
+    pixels inside their rectangles are processed).  ``flip`` (per pixel):
+    differentiate the other branch of the pixel's first flagged decision.
     """
     g = _g64(g)
     n = g["means"].shape[0]
@@ -258,7 +295,7 @@ def backward(g: dict, cams, st: Settings, dl_di, binned=None, sel=None, want_2d=
     lib().orc_backward(n, _p(g["means"]), _p(g["scales"]), _p(g["quats"]), _p(g["opacity"]),
                        _p(g["intensity"]), len(cams), cam_array(cams), C.byref(s), _p(dl),
                        1 if binned is not None else 0, _p(vals), _p(rng), _p(sl),
-                       _p(out["means"]), _p(out["scales"]), _p(out["quats"]),
+                       _p(_u8(flip)), _p(out["means"]), _p(out["scales"]), _p(out["quats"]),
                        _p(out["opacity"]), _p(out["intensity"]), _p(g2d))
     if want_2d:
         out["g2d"] = g2d

@@ -42,7 +42,7 @@
 #include <omp.h>
 #endif
 
-#define ORC_ABI 3
+#define ORC_ABI 4
 
 typedef struct {
     float rot[9];     /* rotation block of M_ext, row-major (Eq. 12) */
@@ -387,9 +387,11 @@ typedef struct {
     int32_t ncontrib;
 } pix_result;
 
+/* flip != 0 renders the other branch of the pixel's first flagged decision
+ * (the second admissible result of a pixel with one flagged decision). */
 static void blend_pixel(int32_t px, int32_t py, const int32_t *order, int64_t len,
                         const orc_proj *pr, const double *opacity, const double *inten,
-                        const orc_set *st, pix_result *res, contrib_t *out_list)
+                        const orc_set *st, int flip, pix_result *res, contrib_t *out_list)
 {
     double T = 1.0, C = 0.0;
     double amin = st->alpha_min, amax = st->alpha_max, tmin = st->t_min;
@@ -407,14 +409,27 @@ static void blend_pixel(int32_t px, int32_t py, const int32_t *order, int64_t le
         double G = exp(power);
         double a = opacity[j] * G;
         int clamped = a > amax;
+        if (fabs(a - amax) <= DELTA_CLAMP * amax) {
+            flags |= FLAG_CLAMP;
+            if (++nflag == 1 && flip) clamped = !clamped;
+        }
         double alpha = clamped ? amax : a;
-        if (fabs(a - amax) <= DELTA_CLAMP * amax) { flags |= FLAG_CLAMP; ++nflag; }
+        int skip = alpha < amin;
         /* a zero threshold cannot be crossed by rounding (alpha >= 0, T >= 0) */
-        if (amin > 0.0 && fabs(alpha - amin) <= DELTA_ALPHA * amin) { flags |= FLAG_ALPHA_MIN; ++nflag; }
-        if (alpha < amin) continue;
+        if (amin > 0.0 && fabs(alpha - amin) <= DELTA_ALPHA * amin) {
+            flags |= FLAG_ALPHA_MIN;
+            if (++nflag == 1 && flip) skip = !skip;
+        }
+        if (skip) continue;
         double Tn = T * (1.0 - alpha);
-        if (tmin > 0.0 && fabs(Tn - tmin) <= DELTA_T * tmin) { flags |= FLAG_T_MIN; ++nflag; }
-        if (Tn < tmin) break;
+        int stop = Tn < tmin;
+        if (tmin > 0.0 && fabs(Tn - tmin) <= DELTA_T * tmin) {
+            flags |= FLAG_T_MIN;
+            if (++nflag == 1 && flip) stop = !stop;
+        }
+        /* the Gaussian that would take T below t_min is not blended, and
+         * blending ends there */
+        if (stop) break;
         if (out_list) {
             contrib_t *cb = &out_list[nc];
             cb->idx = j; cb->pos = (int32_t)k; cb->alpha = alpha; cb->a = a; cb->G = G;
@@ -458,7 +473,7 @@ static int64_t depth_order(int32_t n, const orc_proj *pr, int32_t *order)
  * index of the last contributor (-1 if none). */
 void orc_render_brute(int32_t n, const double *means, const double *scales, const double *quats,
                       const double *opacity, const double *inten, const orc_cam *c,
-                      const orc_set *st, int64_t npix, const int32_t *pix,
+                      const orc_set *st, int64_t npix, const int32_t *pix, const uint8_t *flip,
                       double *img, double *tfin, int32_t *last, int32_t *evals, int32_t *flags)
 {
     orc_proj *pr = (orc_proj *)malloc(sizeof(orc_proj) * (size_t)(n > 0 ? n : 1));
@@ -469,7 +484,7 @@ void orc_render_brute(int32_t n, const double *means, const double *scales, cons
     for (int64_t k = 0; k < npix; ++k) {
         int32_t px = pix[k] % c->width, py = pix[k] / c->width;
         pix_result r;
-        blend_pixel(px, py, order, len, pr, opacity, inten, st, &r, NULL);
+        blend_pixel(px, py, order, len, pr, opacity, inten, st, flip ? flip[k] : 0, &r, NULL);
         img[k] = r.I;
         tfin[k] = r.T;
         if (last) last[k] = r.last_idx;
@@ -483,10 +498,14 @@ void orc_render_brute(int32_t n, const double *means, const double *scales, cons
 /* Binned forward over all pixels of all views: each pixel traverses its
  * tile's sorted list (values[ranges[2g] .. ranges[2g+1]]).  ncontrib is
  * the 1-based list position of the last contributor (0 if none).  Output
- * arrays are the views' images concatenated, row-major. */
+ * arrays are the views' images concatenated, row-major.  flip (nullable,
+ * per pixel): render the other branch of the pixel's first flagged
+ * decision; only (nullable, per pixel): process just the pixels where it is
+ * nonzero, leaving the outputs of the others untouched. */
 void orc_render_binned(int32_t n, const double *means, const double *scales, const double *quats,
                        const double *opacity, const double *inten, int32_t nv, const orc_cam *cams,
                        const orc_set *st, const uint32_t *values, const uint32_t *ranges,
+                       const uint8_t *flip, const uint8_t *only,
                        double *img, double *tfin, int32_t *ncontrib, int32_t *evals, int32_t *flags)
 {
     orc_proj *pr = (orc_proj *)malloc(sizeof(orc_proj) * (size_t)(n > 0 ? n : 1));
@@ -500,12 +519,13 @@ void orc_render_binned(int32_t n, const double *means, const double *scales, con
         #pragma omp parallel for schedule(dynamic, 1)
         for (int32_t py = 0; py < H; ++py) {
             for (int32_t px = 0; px < W; ++px) {
+                int64_t o = poff + (int64_t)py * W + px;
+                if (only && !only[o]) continue;
                 int64_t g = toff + (int64_t)(py / T) * txn + px / T;
                 uint32_t s = ranges[2 * g], e = ranges[2 * g + 1];
                 pix_result r;
                 blend_pixel(px, py, (const int32_t *)(values + s), (int64_t)e - s, pr, opacity,
-                            inten, st, &r, NULL);
-                int64_t o = poff + (int64_t)py * W + px;
+                            inten, st, flip ? flip[o] : 0, &r, NULL);
                 img[o] = r.I;
                 tfin[o] = r.T;
                 if (ncontrib) ncontrib[o] = r.last_pos + 1;
@@ -555,6 +575,64 @@ static void pixel_adjoint(double g, const contrib_t *cl, int32_t nc, const orc_p
             o[q] += v[q];
         }
     }
+}
+
+/* Per 8 x 8 pixel block of every view (blocks at multiples of 8 from the
+ * view's origin, clipped at its edges): the number of distinct Gaussians
+ * that are a contributor of at least one pixel of the block, i.e. the
+ * Gaussians whose gradient terms a block-sized group of pixels sums.
+ * Written at the block's first pixel (concatenated image layout); every
+ * other pixel gets 0.  Pixels traverse their tiles' lists (values, ranges). */
+void orc_block_contributors(int32_t n, const double *means, const double *scales,
+                            const double *quats, const double *opacity, const double *inten,
+                            int32_t nv, const orc_cam *cams, const orc_set *st,
+                            const uint32_t *values, const uint32_t *ranges, int32_t *out)
+{
+    int32_t nn = n > 0 ? n : 1;
+    orc_proj *pr = (orc_proj *)malloc(sizeof(orc_proj) * (size_t)nn);
+    int64_t poff = 0, toff = 0;
+    int32_t T = st->tile;
+    for (int32_t v = 0; v < nv; ++v) {
+        const orc_cam *c = &cams[v];
+        int32_t W = c->width, H = c->height;
+        orc_project(n, means, scales, quats, opacity, c, st, pr);
+        int32_t txn = tiles_x(c, T);
+        int32_t bw = (W + 7) / 8, bh = (H + 7) / 8;
+        memset(out + poff, 0, sizeof(int32_t) * (size_t)W * H);
+        int64_t ntv = (int64_t)txn * tiles_y(c, T), longest = 1;
+        for (int64_t g = toff; g < toff + ntv; ++g)
+            if ((int64_t)(ranges[2 * g + 1] - ranges[2 * g]) > longest)
+                longest = (int64_t)(ranges[2 * g + 1] - ranges[2 * g]);
+        #pragma omp parallel
+        {
+            contrib_t *cl = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)longest);
+            int64_t *seen = (int64_t *)malloc(sizeof(int64_t) * (size_t)nn);
+            for (int32_t i = 0; i < nn; ++i) seen[i] = -1;
+            #pragma omp for schedule(dynamic, 1)
+            for (int32_t by = 0; by < bh; ++by) {
+                for (int32_t bx = 0; bx < bw; ++bx) {
+                    int64_t blk = (int64_t)by * bw + bx;
+                    int32_t cnt = 0;
+                    for (int32_t py = 8 * by; py < 8 * by + 8 && py < H; ++py)
+                        for (int32_t px = 8 * bx; px < 8 * bx + 8 && px < W; ++px) {
+                            int64_t gt = toff + (int64_t)(py / T) * txn + px / T;
+                            uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
+                            pix_result r;
+                            blend_pixel(px, py, (const int32_t *)(values + s), (int64_t)e - s, pr,
+                                        opacity, inten, st, 0, &r, cl);
+                            for (int32_t m = 0; m < r.ncontrib; ++m)
+                                if (seen[cl[m].idx] != blk) { seen[cl[m].idx] = blk; ++cnt; }
+                        }
+                    out[poff + (int64_t)(8 * by) * W + 8 * bx] = cnt;
+                }
+            }
+            free(seen);
+            free(cl);
+        }
+        poff += (int64_t)W * H;
+        toff += (int64_t)txn * tiles_y(c, T);
+    }
+    free(pr);
 }
 
 /* Chain rule from the 2-D gradients of one (view, Gaussian) to the 3-D
@@ -664,6 +742,7 @@ void orc_backward(int32_t n, const double *means, const double *scales, const do
                   const double *opacity, const double *inten, int32_t nv, const orc_cam *cams,
                   const orc_set *st, const float *dl_di, int32_t binned,
                   const uint32_t *values, const uint32_t *ranges, const uint8_t *sel,
+                  const uint8_t *flip,
                   double *g_means, double *g_scales, double *g_quats, double *g_opac,
                   double *g_inten, double *g2d_out)
 {
@@ -701,13 +780,14 @@ void orc_backward(int32_t n, const double *means, const double *scales, const do
                     double g = (double)dl_di[poff + o];
                     if (g == 0.0) continue;
                     pix_result r;
+                    int fl = flip ? flip[poff + o] : 0;
                     if (binned) {
                         int64_t gt = toff + (int64_t)(py / T) * txn + px / T;
                         uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
                         blend_pixel(px, py, (const int32_t *)(values + s), (int64_t)e - s, pr,
-                                    opacity, inten, st, &r, cl);
+                                    opacity, inten, st, fl, &r, cl);
                     } else {
-                        blend_pixel(px, py, order, len, pr, opacity, inten, st, &r, cl);
+                        blend_pixel(px, py, order, len, pr, opacity, inten, st, fl, &r, cl);
                     }
                     pixel_adjoint(g, cl, r.ncontrib, pr, inten, g2d);
                 }
