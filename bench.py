@@ -40,12 +40,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# algorithmic float32 operations (FMA = 2) per unit of work, counted from the
-# definition of Eq. 10 and its adjoint (see the design notes)
-FLOPS_EVAL = 14          # one alpha evaluation at a pixel (offset, exponent, exp, clamp, test)
-FLOPS_BLEND = 6          # blending a contributor (transmittance update, test, accumulate)
-FLOPS_ADJOINT = 28       # adjoint of one contributor (transmittance recovery, 7 gradients)
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
+# Algorithmic work of the blend kernels in VALU lane-operation cycles (a
+# transcendental counts 4: quarter rate), per unit of work of the definition:
+#   forward: 21 per evaluation (offset, exponent, exp, opacity, clamp, test,
+#            transmittance update, accumulate);
+#   backward: 35 per revisited evaluation (recompute alpha, recover T by
+#            division, the 7 gradient terms) plus, per (Gaussian, wavefront)
+#            with a contributing lane, 42 wavefront instructions (the 7-value
+#            wavefront reduction and its atomics) = 42 x 64 lane slots.
+LANE_OPS_EVAL_FWD = 21
+LANE_OPS_EVAL_BWD = 35
+WAVE_INSTR_REDUCTION = 42
+WAVE = 64
+# MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.3 T lane-operations/s without
+# packed FP32 (what these scalar-FP32 kernels can issue); the published FP32
+# vector peak, 157.3 TFLOP/s, counts an FMA as 2 and packed FP32 (2 per lane).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_BPS = 8.0e12     # MI355X HBM3E
 # Eq. 11 loss gradient, algorithmic bytes per pixel: image + target read twice
 # (16), three SSIM derivative maps written then read (24), dl written (4)
@@ -359,11 +370,12 @@ def main():
                                loss_val.data_ptr(), sid)
             mark(record, row)
         if store is None:
-            P.xg_render_bwd(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), sid)
+            X.xg_render_bwd_2d(frame.frame, dl.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(),
+                               sid)
         else:
-            X.xg_render_bwd_store(frame.frame, dl.data_ptr(), final_t.data_ptr(),
-                                  n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
-                                  store.view.numel(), sid)
+            X.xg_render_bwd_store_2d(frame.frame, dl.data_ptr(), final_t.data_ptr(),
+                                     n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
+                                     store.view.numel(), sid)
         mark(record, row)
         if write_grads:
             X.xg_preprocess_bwd_write(frame.frame, gs, gr, sid)
@@ -404,14 +416,20 @@ def main():
     bwd_ms = stage_ms["render_bwd"]
 
     counts = frame.render_counts().double().sum(dim=1).cpu().numpy()
-    evals, contribs, upto = (float(x) for x in counts)
-    fwd_flops = evals * FLOPS_EVAL + contribs * FLOPS_BLEND
-    bwd_flops = upto * FLOPS_EVAL + contribs * FLOPS_ADJOINT
+    evals, contribs, upto, reductions, bwd_visits, fwd_visits, fwd_lane_evals, bwd_lane_evals = \
+        (float(x) for x in counts)
+    fwd_ops = evals * LANE_OPS_EVAL_FWD
+    bwd_ops = upto * LANE_OPS_EVAL_BWD + reductions * WAVE_INSTR_REDUCTION * WAVE
     if bwd_ms >= fwd_ms:
-        dom, dom_ms, dom_flops = "k_render_bwd", bwd_ms, bwd_flops
+        dom, dom_ms, dom_ops = "k_render_bwd", bwd_ms, bwd_ops
     else:
-        dom, dom_ms, dom_flops = "k_render_fwd", fwd_ms, fwd_flops
-    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+        dom, dom_ms, dom_ops = "k_render_fwd", fwd_ms, fwd_ops
+    achieved = dom_ops / (dom_ms * 1e-3)
+    lanes = {
+        "fwd_visits": fwd_visits, "fwd_active_lanes_per_visit": fwd_lane_evals / max(fwd_visits, 1),
+        "bwd_visits": bwd_visits, "bwd_active_lanes_per_visit": bwd_lane_evals / max(bwd_visits, 1),
+        "bwd_reductions": reductions, "bwd_contributing_lanes_per_reduction": contribs / max(reductions, 1),
+    }
 
     # per-stage algorithmic work and fraction of the stage's roofline
     n_items = w.n * w.n_views
@@ -425,11 +443,11 @@ def main():
         "preprocess": ("hbm", 48 * w.n + (64 + 4 + 8 + 32) * n_items),
         "bin_sort": ("hbm", n_items * (4 + 16 * item_passes + 8 + 12) + 16 * n_kept
                      + npairs * (8 + 4 + 16 * pair_passes + 4) + 8 * frame.total_tiles),
-        "render_fwd": ("alu", fwd_flops),
-        "render_fwd_l1": ("alu", fwd_flops),   # plus 12 bytes per pixel for the L1 epilogue
+        "render_fwd": ("alu", fwd_ops),
+        "render_fwd_l1": ("alu", fwd_ops),   # plus 12 bytes per pixel for the L1 epilogue
         "l1_grad": ("hbm", 12 * npx),
         "loss_grad": ("hbm", LOSS_BYTES_PER_PX * npx),
-        "render_bwd": ("alu", bwd_flops),
+        "render_bwd": ("alu", bwd_ops),
         "preprocess_bwd": ("hbm", 32 * n_items + 144 * w.n),
         "adam": ("hbm", 12 * w.n * 30),
     }
@@ -439,8 +457,8 @@ def main():
         ms = stage_ms[name]
         rate = wk / (ms * 1e-3)
         stages[name] = {"ms": ms, "bound": bound, "work": wk,
-                        "unit": "bytes" if bound == "hbm" else "flop",
-                        "frac": rate / (PEAK_HBM_BPS if bound == "hbm" else PEAK_FP32_TFLOPS * 1e12)}
+                        "unit": "bytes" if bound == "hbm" else "lane-op",
+                        "frac": rate / (PEAK_HBM_BPS if bound == "hbm" else PEAK_LANE_OPS)}
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
@@ -499,8 +517,7 @@ def main():
                     P.xg_render_fwd(f.frame, gs, im.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
                     P.xg_l1_grad(im.data_ptr(), tg.data_ptr(), d.data_ptr(), n, scale, sid)
                 # the views' gradients add up: cleared once, accumulated per view
-                P.xg_render_bwd(f.frame, d.data_ptr(), ft.data_ptr(), nc.data_ptr(), sid)
-                P.xg_preprocess_bwd(f.frame, gs, gr, sid)
+                P.xg_render_bwd(f.frame, gs, d.data_ptr(), ft.data_ptr(), nc.data_ptr(), gr, sid)
 
         ms_pv, _ = timed(step_per_view, args.steps, args.warmup)
         per_view = {"value": w.n_views / (ms_pv * 1e-3), "ms_per_step": ms_pv}
@@ -565,26 +582,46 @@ def main():
     if not args.no_cpu:
         import oracle as O
         st_o = O.Settings(tile=args.tile)
+        ocams = [O.camera(w.angles[v], S.L_SO, S.L_SD, w.sizes[v][0], w.sizes[v][1], D, D)
+                 for v in range(w.n_views)]
+        # the L1 targets are inputs of the step (the GPU renders them once,
+        # outside timing): rendered here before the timed region too, for the
+        # views the time budget can reach
+        per_view_s = None
+        targets = {}
         done_views = 0
-        t0 = time.perf_counter()
-        # views in order, cycling, until the time budget is spent (at least one)
+        timed_s = 0.0
+        # views in order, cycling, until the time budget is spent (at least one);
+        # timed per view: pair emission + sort, binned forward, L1 upstream,
+        # binned adjoint to every parameter -- the GPU step's work
         while True:
             v = done_views % w.n_views
-            c = O.camera(w.angles[v], S.L_SO, S.L_SD, w.sizes[v][0], w.sizes[v][1], D, D)
+            c = ocams[v]
+            if v not in targets:
+                prt = O.pairs(tgt_np, [c], st_o)
+                targets[v] = O.render_binned(tgt_np, [c], st_o, prt["values"], prt["ranges"])["image"]
+            t0 = time.perf_counter()
             pr = O.pairs(g_np, [c], st_o)
             r = O.render_binned(g_np, [c], st_o, pr["values"], pr["ranges"])
-            prt = O.pairs(tgt_np, [c], st_o)
-            rt = O.render_binned(tgt_np, [c], st_o, prt["values"], prt["ranges"])
-            up = (np.sign(r["image"] - rt["image"]) * scale).astype(np.float32)
+            up = (np.sign(r["image"] - targets[v]) * scale).astype(np.float32)
             O.backward(g_np, [c], st_o, up, binned=(pr["values"], pr["ranges"]))
+            timed_s += time.perf_counter() - t0
             done_views += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
+            if timed_s >= args.cpu_seconds:
                 break
-        el = time.perf_counter() - t0
-        cpu = {"value": done_views / el, "unit": "views/s", "cores": O.threads(), "kind": "oracle",
-               "sample": f"{done_views} view passes (views 0..{w.n_views - 1} in turn), each: pair "
-                         f"emission + sort, binned forward, target forward, binned adjoint "
-                         f"(FP64), {el:.1f} s"}
+        model = "unknown"
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu = {"value": done_views / timed_s, "unit": "views/s", "cores": O.threads(),
+               "cpu_model": model, "kind": "oracle",
+               "sample": f"{done_views} view passes (views 0..{w.n_views - 1} in turn; timed: pair "
+                         f"emission + sort, binned forward, L1 upstream, binned adjoint, FP64; the "
+                         f"targets rendered before timing), {timed_s:.1f} s timed"}
 
     if args.workload == 3:
         metric = "DRR fwd+bwd views/s at 512^2, 200k Gaussians; batched vs per-view, same GPU"
@@ -610,9 +647,14 @@ def main():
                    "detector": "x".join(map(str, w.sizes[0])) if len(set(w.sizes)) == 1 else "mixed",
                    "tile": args.tile, "lds_batch": args.lds, "persistent": bool(args.persistent),
                    "store_slots": args.store, "adam": opt is not None, "path": "batched"},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "launch_ms": dom_ms, "flops_per_launch": dom_flops},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
+                     "frac": achieved / PEAK_LANE_OPS,
+                     "frac_of_fp32_flops_peak": achieved / (PEAK_FP32_TFLOPS * 1e12),
+                     "traffic": traffic, "launch_ms": dom_ms, "lane_ops_per_launch": dom_ops,
+                     "work_model": f"fwd {LANE_OPS_EVAL_FWD}/evaluation; bwd {LANE_OPS_EVAL_BWD}/"
+                                   f"revisited evaluation + {WAVE_INSTR_REDUCTION} x {WAVE} per "
+                                   "(Gaussian, wavefront) reduction"},
         "cpu_baseline": cpu,
         "graph": graph,
         "per_view": per_view,
@@ -624,7 +666,8 @@ def main():
         "acui_forward": acui,
         "rgb_forward": rgb,
         "work": {"pairs": n_pairs, "evals": evals, "contributors": contribs,
-                 "revisited": upto},
+                 "revisited": upto, "reductions": reductions},
+        "lanes": lanes,
         "evals_per_s": evals * w.n_views / w.n_views / (ms_batched * 1e-3),
         "wall_s": wall_b,
         "kernel_source_hash": kernel_source_hash(),

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define XG_ABI_VERSION 3
+#define XG_ABI_VERSION 4
 
 typedef enum {
     XG_OK = 0,
@@ -87,7 +87,8 @@ typedef struct {
     int32_t n;
 } xg_gaussians;
 
-/* Gradients of the same shapes; xg_preprocess_bwd ACCUMULATES (+=) into them. */
+/* Gradients of the same shapes; xg_render_bwd and xg_preprocess_bwd
+ * ACCUMULATE (+=) into them. */
 typedef struct {
     float *means, *scales, *quats, *opacity, *intensity;
 } xg_grads;
@@ -213,16 +214,29 @@ xg_status xg_render_fwd_l1(const xg_frame *f /* [host] */, const xg_gaussians *g
                            float *image, float *final_t, int32_t *n_contrib, const float *target,
                            float scale, float *dl_dimage, void *stream);
 
-/* Stage 4 (adjoint of Eq. 10): walks each pixel's list backwards from
- * n_contrib, recovering the transmittance by division instead of reading
- * stored per-contributor values, and accumulates per (view, Gaussian) the
- * 2-D gradients (image-space centre, inverse 2-D covariance, opacity,
- * intensity) in the workspace, reduced across each wavefront before one
- * atomic add per (Gaussian, wavefront).  dl_dimage has the image layout;
- * final_t and n_contrib are the forward's outputs.  Call once per
- * xg_preprocess (which clears the accumulators). */
-xg_status xg_render_bwd(const xg_frame *f /* [host] */, const float *dl_dimage,
-                        const float *final_t, const int32_t *n_contrib, void *stream);
+/* Stage 4 (adjoint of Eq. 10 and of Eq. 7-9): the gradient of
+ * L = sum_p dl_dimage[p] I(p) with respect to every Gaussian parameter,
+ * ADDED to `grads` (the caller zeroes them).  Runs xg_render_bwd_2d, then
+ * xg_preprocess_bwd.  dl_dimage has the image layout; final_t and
+ * n_contrib are the outputs of the forward of this frame since the last
+ * xg_preprocess.  Recomputes the transmittance by division (only the final
+ * T and the last contributor are kept from the forward).  Call once per
+ * xg_preprocess (which clears the 2-D accumulators).  EINVAL: as
+ * xg_render_bwd_2d and xg_preprocess_bwd, checked before anything is
+ * enqueued. */
+xg_status xg_render_bwd(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                        const float *dl_dimage, const float *final_t, const int32_t *n_contrib,
+                        const xg_grads *grads /* [host] struct of device ptrs */, void *stream);
+
+/* The first half of xg_render_bwd (adjoint of Eq. 10 alone): walks each
+ * pixel's list backwards from n_contrib, recovering the transmittance by
+ * division instead of reading stored per-contributor values, and
+ * accumulates per (view, Gaussian) the 2-D gradients (image-space centre,
+ * inverse 2-D covariance moments, opacity, intensity) in the workspace,
+ * reduced across each wavefront before one atomic add per (Gaussian,
+ * wavefront).  Follow with xg_preprocess_bwd or xg_preprocess_bwd_write. */
+xg_status xg_render_bwd_2d(const xg_frame *f /* [host] */, const float *dl_dimage,
+                           const float *final_t, const int32_t *n_contrib, void *stream);
 
 /* Stored-transmittance variant of stages 3 and 4.  The forward
  * additionally keeps, for every pixel, the transmittance in front of each
@@ -241,9 +255,16 @@ xg_status xg_store_size(const xg_frame *f /* [host] */, int32_t slots, int64_t *
 xg_status xg_render_fwd_store(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                               float *image, float *final_t, int32_t *n_contrib, void *store,
                               int32_t slots, int64_t store_bytes, void *stream);
-xg_status xg_render_bwd_store(const xg_frame *f /* [host] */, const float *dl_dimage,
-                              const float *final_t, const int32_t *n_contrib, const void *store,
-                              int32_t slots, int64_t store_bytes, void *stream);
+/* xg_render_bwd with the stored transmittances: the 2-D stage
+ * (xg_render_bwd_store_2d) then xg_preprocess_bwd, adding to `grads`. */
+xg_status xg_render_bwd_store(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
+                              const float *dl_dimage, const float *final_t,
+                              const int32_t *n_contrib, const void *store, int32_t slots,
+                              int64_t store_bytes, const xg_grads *grads /* [host] */, void *stream);
+/* The 2-D stage alone (as xg_render_bwd_2d, reading the store). */
+xg_status xg_render_bwd_store_2d(const xg_frame *f /* [host] */, const float *dl_dimage,
+                                 const float *final_t, const int32_t *n_contrib, const void *store,
+                                 int32_t slots, int64_t store_bytes, void *stream);
 
 /* Stage 5 (adjoint of Eq. 7-9): maps the 2-D gradients of every view to
  * means, scales, quaternions (through their normalisation), opacity and
@@ -256,13 +277,57 @@ xg_status xg_preprocess_bwd(const xg_frame *f /* [host] */, const xg_gaussians *
 xg_status xg_preprocess_bwd_write(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                                   const xg_grads *grads /* [host] */, void *stream);
 
-/* Per-pixel work counts of the forward definition, for throughput
- * accounting and tests: counts[0][p] = evaluations (Gaussians of the list
- * whose rectangle holds p, visited up to and including the one that ends
- * blending), counts[1][p] = contributors, counts[2][p] = evaluations up to
- * the last contributor (what the backward revisits).  counts is int32
- * [3][total pixels]. */
+/* Work counts, for throughput accounting and tests.  counts is int32
+ * [XG_COUNT_ROWS][total pixels] (device).  Rows 0-3 follow from the
+ * definition of Eq. 10 and the sorted lists alone; rows 4-7 describe how
+ * the blending kernels walk the lists (wavefronts of 8 x 8 pixel blocks,
+ * 8-aligned in each view; entries whose footprint cannot reach alpha_min
+ * anywhere in the block are not visited).  "Per block" rows hold the
+ * block's value at its first pixel and 0 at its other pixels.
+ *   0: per pixel, evaluations: Gaussians of the list whose rectangle holds
+ *      the pixel, up to and including the one that ends blending
+ *   1: per pixel, contributors
+ *   2: per pixel, evaluations up to the last contributor (what the
+ *      backward revisits)
+ *   3: per block, Gaussians that contribute to at least one pixel of the
+ *      block (the backward's wavefront reductions)
+ *   4: per block, list entries the backward wavefront visits (up to the
+ *      block's last contributing entry; every pixel's upstream gradient
+ *      taken as nonzero)
+ *   5: per block, list entries the forward wavefront visits (up to the
+ *      entry at which the block's last pixel stops, or the list end)
+ *   6: per pixel, evaluations the forward makes for it in those visits
+ *   7: per pixel, evaluations the backward makes for it in its visits (in
+ *      the rectangle, up to the pixel's last contributor) */
+#define XG_COUNT_ROWS 8
 xg_status xg_render_counts(const xg_frame *f /* [host] */, int32_t *counts, void *stream);
+
+/* Device pointers into a frame's workspace, for inspection and tests (no
+ * HIP call; read them after synchronising with the stream that wrote
+ * them).  pair_tiles/pair_values as in xg_ws_layout; ranges
+ * uint32[total_tiles][2]; records 64-byte render records per (view,
+ * Gaussian); grad2d float[n_views*n][8].  The workspace holds no 64-bit
+ * sort keys (the lists are built by two 32-bit sorts); xg_pair_keys writes
+ * them out. */
+typedef struct {
+    const int32_t *status, *n_pairs;
+    const uint32_t *pair_tiles, *pair_values, *ranges;
+    const void *records;
+    const float *grad2d;
+    int32_t pair_index_bits;
+    int64_t total_tiles, total_pixels;
+} xg_ws_view;
+xg_status xg_ws_inspect(const xg_frame *f /* [host] */, xg_ws_view *out /* [host] */);
+
+/* The sorted lists as (key, value) pairs (Sec. 3.2): for every sorted pair
+ * p below the device pair count, keys[p] = (global tile id << 32) | float32
+ * bits of the camera depth of (view of that tile, Gaussian), values[p] =
+ * Gaussian index, ascending by (key, value).  keys uint64[capacity] and
+ * values uint32[capacity] are device buffers; pairs past `capacity` and
+ * entries past the pair count are not written; nothing is written when the
+ * status word is not XG_OK.  EINVAL: null buffers, capacity < 0. */
+xg_status xg_pair_keys(const xg_frame *f /* [host] */, uint64_t *keys, uint32_t *values,
+                       int64_t capacity, void *stream);
 
 /* Radiation intensity response (Eq. 3): each Gaussian has a feature
  * vector f[n_features] and its intensity is sigmoid(sum_k w[k] f[k]) with

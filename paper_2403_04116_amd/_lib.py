@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libxg.so")
 
 XG_OK, XG_EINVAL, XG_ECAPACITY, XG_EHIP = 0, 1, 2, 3
 XG_F_PERSISTENT = 1
-ABI_VERSION = 3
+ABI_VERSION = 4
+COUNT_ROWS = 8
 MAX_FEATURES = 64
 
 
@@ -83,6 +84,13 @@ class XgWsLayout(C.Structure):
         "pair_values", "ranges", "grad2d", "total", "pair_index_bits")]
 
 
+class XgWsView(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("n_pairs", C.c_void_p), ("pair_tiles", C.c_void_p),
+                ("pair_values", C.c_void_p), ("ranges", C.c_void_p), ("records", C.c_void_p),
+                ("grad2d", C.c_void_p), ("pair_index_bits", C.c_int32), ("total_tiles", C.c_int64),
+                ("total_pixels", C.c_int64)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "(the DRR path has no CPU fallback)")
@@ -112,7 +120,14 @@ _L.xg_bin_sort.argtypes = [C.POINTER(XgFrame), _P]
 _L.xg_render_fwd.restype = _S
 _L.xg_render_fwd.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P]
 _L.xg_render_bwd.restype = _S
-_L.xg_render_bwd.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P]
+_L.xg_render_bwd.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P,
+                             C.POINTER(XgGrads), _P]
+_L.xg_render_bwd_2d.restype = _S
+_L.xg_render_bwd_2d.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P]
+_L.xg_ws_inspect.restype = _S
+_L.xg_ws_inspect.argtypes = [C.POINTER(XgFrame), C.POINTER(XgWsView)]
+_L.xg_pair_keys.restype = _S
+_L.xg_pair_keys.argtypes = [C.POINTER(XgFrame), _P, _P, C.c_int64, _P]
 _L.xg_preprocess_bwd.restype = _S
 _L.xg_preprocess_bwd.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), C.POINTER(XgGrads), _P]
 _L.xg_render_counts.restype = _S
@@ -127,7 +142,10 @@ _L.xg_render_fwd_store.restype = _S
 _L.xg_render_fwd_store.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P,
                                    C.c_int32, C.c_int64, _P]
 _L.xg_render_bwd_store.restype = _S
-_L.xg_render_bwd_store.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P, C.c_int32, C.c_int64, _P]
+_L.xg_render_bwd_store.argtypes = [C.POINTER(XgFrame), C.POINTER(XgGaussians), _P, _P, _P, _P,
+                                   C.c_int32, C.c_int64, C.POINTER(XgGrads), _P]
+_L.xg_render_bwd_store_2d.restype = _S
+_L.xg_render_bwd_store_2d.argtypes = [C.POINTER(XgFrame), _P, _P, _P, _P, C.c_int32, C.c_int64, _P]
 _L.xg_rirf_fwd.restype = _S
 _L.xg_rirf_fwd.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P]
 _L.xg_rirf_bwd.restype = _S
@@ -161,7 +179,8 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_render_counts", "xg_l1_grad", "xg_last_error", "xg_adam_step", "xg_store_size",
             "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd",
             "xg_loss_grad", "xg_acui_count", "xg_acui_grid", "xg_preprocess_rgb",
-            "xg_render_fwd_rgb", "xg_render_fwd_l1", "xg_preprocess_bwd_write")
+            "xg_render_fwd_rgb", "xg_render_fwd_l1", "xg_preprocess_bwd_write", "xg_render_bwd_2d",
+            "xg_render_bwd_store_2d", "xg_ws_inspect", "xg_pair_keys")
 MAX_STORE_SLOTS = 4096
 
 
@@ -249,16 +268,39 @@ def xg_render_fwd_store(frame: XgFrame, g: XgGaussians, image: int, final_t: int
                                   slots, store_bytes, stream), "xg_render_fwd_store")
 
 
-def xg_render_bwd_store(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int, store: int,
-                        slots: int, store_bytes: int, stream: int = 0) -> None:
-    _check(_L.xg_render_bwd_store(C.byref(frame), dl_dimage, final_t, n_contrib, store, slots,
-                                  store_bytes, stream), "xg_render_bwd_store")
+def xg_render_bwd_store(frame: XgFrame, g: XgGaussians, dl_dimage: int, final_t: int,
+                        n_contrib: int, store: int, slots: int, store_bytes: int, grads: XgGrads,
+                        stream: int = 0) -> None:
+    _check(_L.xg_render_bwd_store(C.byref(frame), C.byref(g), dl_dimage, final_t, n_contrib, store,
+                                  slots, store_bytes, C.byref(grads), stream), "xg_render_bwd_store")
 
 
-def xg_render_bwd(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int,
-                  stream: int = 0) -> None:
-    _check(_L.xg_render_bwd(C.byref(frame), dl_dimage, final_t, n_contrib, stream),
-           "xg_render_bwd")
+def xg_render_bwd_store_2d(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int, store: int,
+                           slots: int, store_bytes: int, stream: int = 0) -> None:
+    _check(_L.xg_render_bwd_store_2d(C.byref(frame), dl_dimage, final_t, n_contrib, store, slots,
+                                     store_bytes, stream), "xg_render_bwd_store_2d")
+
+
+def xg_render_bwd(frame: XgFrame, g: XgGaussians, dl_dimage: int, final_t: int, n_contrib: int,
+                  grads: XgGrads, stream: int = 0) -> None:
+    _check(_L.xg_render_bwd(C.byref(frame), C.byref(g), dl_dimage, final_t, n_contrib,
+                            C.byref(grads), stream), "xg_render_bwd")
+
+
+def xg_render_bwd_2d(frame: XgFrame, dl_dimage: int, final_t: int, n_contrib: int,
+                     stream: int = 0) -> None:
+    _check(_L.xg_render_bwd_2d(C.byref(frame), dl_dimage, final_t, n_contrib, stream),
+           "xg_render_bwd_2d")
+
+
+def xg_ws_inspect(frame: XgFrame) -> XgWsView:
+    out = XgWsView()
+    _check(_L.xg_ws_inspect(C.byref(frame), C.byref(out)), "xg_ws_inspect")
+    return out
+
+
+def xg_pair_keys(frame: XgFrame, keys: int, values: int, capacity: int, stream: int = 0) -> None:
+    _check(_L.xg_pair_keys(C.byref(frame), keys, values, capacity, stream), "xg_pair_keys")
 
 
 def xg_preprocess_bwd(frame: XgFrame, g: XgGaussians, grads: XgGrads, stream: int = 0) -> None:

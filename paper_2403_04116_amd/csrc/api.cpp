@@ -376,8 +376,17 @@ xg_status xg_render_fwd_l1(const xg_frame *f, const xg_gaussians *g, float *imag
     return render_fwd_common(f, g, image, final_t, n_contrib, L1Fuse{target, dl_dimage, scale}, stream);
 }
 
-xg_status xg_render_bwd(const xg_frame *f, const float *dl_dimage, const float *final_t,
-                        const int32_t *n_contrib, void *stream) {
+static bool valid_grads(const xg_grads *grads, int32_t n) {
+    if (!grads) return false;
+    return n == 0 || (grads->means && grads->scales && grads->quats && grads->opacity &&
+                      grads->intensity);
+}
+
+static xg_status preprocess_bwd_common(const xg_frame *f, const xg_gaussians *g,
+                                       const xg_grads *grads, bool accumulate, void *stream);
+
+xg_status xg_render_bwd_2d(const xg_frame *f, const float *dl_dimage, const float *final_t,
+                           const int32_t *n_contrib, void *stream) {
     Plan P;
     xg_status st = make_plan(f, true, P);
     if (st != XG_OK) return st;
@@ -443,9 +452,22 @@ xg_status xg_render_fwd_store(const xg_frame *f, const xg_gaussians *g, float *i
                                         L1Fuse{nullptr, nullptr, 0.0f}, (hipStream_t)stream));
 }
 
-xg_status xg_render_bwd_store(const xg_frame *f, const float *dl_dimage, const float *final_t,
-                              const int32_t *n_contrib, const void *store, int32_t slots,
-                              int64_t store_bytes, void *stream) {
+xg_status xg_render_bwd(const xg_frame *f, const xg_gaussians *g, const float *dl_dimage,
+                        const float *final_t, const int32_t *n_contrib, const xg_grads *grads,
+                        void *stream) {
+    // validate everything before the first launch, so EINVAL enqueues nothing
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !valid_grads(grads, f->n)) return XG_EINVAL;
+    st = xg_render_bwd_2d(f, dl_dimage, final_t, n_contrib, stream);
+    if (st != XG_OK) return st;
+    return preprocess_bwd_common(f, g, grads, true, stream);
+}
+
+xg_status xg_render_bwd_store_2d(const xg_frame *f, const float *dl_dimage, const float *final_t,
+                                 const int32_t *n_contrib, const void *store, int32_t slots,
+                                 int64_t store_bytes, void *stream) {
     Plan P;
     xg_status st = make_plan(f, true, P);
     if (st != XG_OK) return st;
@@ -459,15 +481,25 @@ xg_status xg_render_bwd_store(const xg_frame *f, const float *dl_dimage, const f
                                         (hipStream_t)stream));
 }
 
+xg_status xg_render_bwd_store(const xg_frame *f, const xg_gaussians *g, const float *dl_dimage,
+                              const float *final_t, const int32_t *n_contrib, const void *store,
+                              int32_t slots, int64_t store_bytes, const xg_grads *grads,
+                              void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!valid_gaussians(g, f->n) || !valid_grads(grads, f->n)) return XG_EINVAL;
+    st = xg_render_bwd_store_2d(f, dl_dimage, final_t, n_contrib, store, slots, store_bytes, stream);
+    if (st != XG_OK) return st;
+    return preprocess_bwd_common(f, g, grads, true, stream);
+}
+
 static xg_status preprocess_bwd_common(const xg_frame *f, const xg_gaussians *g,
                                        const xg_grads *grads, bool accumulate, void *stream) {
     Plan P;
     xg_status st = make_plan(f, true, P);
     if (st != XG_OK) return st;
-    if (!valid_gaussians(g, f->n) || !grads) return XG_EINVAL;
-    if (f->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity ||
-                     !grads->intensity))
-        return XG_EINVAL;
+    if (!valid_gaussians(g, f->n) || !valid_grads(grads, f->n)) return XG_EINVAL;
     if (f->n == 0) return XG_OK;
     const Ws ws = resolve(f, P);
     const Params p = params_of(f->settings);
@@ -483,6 +515,37 @@ xg_status xg_preprocess_bwd(const xg_frame *f, const xg_gaussians *g, const xg_g
 xg_status xg_preprocess_bwd_write(const xg_frame *f, const xg_gaussians *g, const xg_grads *grads,
                                   void *stream) {
     return preprocess_bwd_common(f, g, grads, false, stream);
+}
+
+xg_status xg_ws_inspect(const xg_frame *f, xg_ws_view *out) {
+    if (!out) return XG_EINVAL;
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    const char *b = (const char *)f->ws;
+    memset(out, 0, sizeof(*out));
+    out->status = (const int32_t *)(b + P.lay.status);
+    out->n_pairs = (const int32_t *)(b + P.lay.n_pairs);
+    out->pair_tiles = (const uint32_t *)(b + P.lay.pair_tiles);
+    out->pair_values = (const uint32_t *)(b + P.lay.pair_values);
+    out->ranges = (const uint32_t *)(b + P.lay.ranges);
+    out->records = (const void *)(b + P.lay.records);
+    out->grad2d = (const float *)(b + P.lay.grad2d);
+    out->pair_index_bits = (int32_t)P.lay.pair_index_bits;
+    out->total_tiles = P.total_tiles;
+    out->total_pixels = P.total_px;
+    return XG_OK;
+}
+
+xg_status xg_pair_keys(const xg_frame *f, uint64_t *keys, uint32_t *values, int64_t capacity,
+                       void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, true, P);
+    if (st != XG_OK) return st;
+    if (!keys || !values || capacity < 0) return XG_EINVAL;
+    if (capacity == 0) return XG_OK;
+    const Ws ws = resolve(f, P);
+    return hip_status(launch_pair_keys(ws, f->cams_dev, keys, values, capacity, (hipStream_t)stream));
 }
 
 xg_status xg_render_counts(const xg_frame *f, int32_t *counts, void *stream) {

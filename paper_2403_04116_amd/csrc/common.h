@@ -163,6 +163,8 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s);
 hipError_t launch_ranges(const Ws &ws, bool cleared, hipStream_t s);  // cleared: by the pair sort
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
+hipError_t launch_pair_keys(const Ws &ws, const xg_camera *cams, uint64_t *keys, uint32_t *vals,
+                            int64_t cap, hipStream_t s);
 // Per-pixel stored transmittances of the stored-list variant: count[tile][px]
 // contributors, then t[tile][slot][px] = T before contributor `slot` (the
 // first `slots` contributors of each pixel; px = thread index in the tile).

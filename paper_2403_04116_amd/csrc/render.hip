@@ -116,10 +116,13 @@ __device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, 
 // compared with log2(o / alpha_min) plus a margin far above float
 // rounding.  Dropping the others skips only evaluations that the
 // per-pixel alpha test would skip, so results do not change.
-template <int T, int NT, bool CULL>
+// DUAL (the counting forward): s_mask keeps the rectangle-only mask and
+// s_cmask receives the culled one.
+template <int T, int NT, bool CULL, bool DUAL = false>
 __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32_t b0, int cnt,
                                       const TileGeom &tg, float amin, float4 *s_a, float4 *s_b,
-                                      uint16_t *s_mask, uint32_t *s_rid, float4 *s_c = nullptr) {
+                                      uint16_t *s_mask, uint32_t *s_rid, float4 *s_c = nullptr,
+                                      uint16_t *s_cmask = nullptr) {
     constexpr int SB = T / 8;
     for (int k = threadIdx.x; k < cnt; k += NT) {
         const uint32_t gi = vals[b0 + k] & ws.pair_gmask;   // Gaussian index (packed or not)
@@ -136,7 +139,8 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         s_a[k] = make_float4(ux, uy, ra.z, ra.w);
         s_b[k] = make_float4(rb.x, rb.y, rb.z, __uint_as_float(rect));
         uint32_t m = subblock_mask<SB>(xl, xh, yl, yh);
-        if (CULL) {
+        uint32_t mc = m;
+        if (CULL || DUAL) {
             const float thr = __builtin_amdgcn_logf(rb.y * __builtin_amdgcn_rcpf(amin)) * 1.00001f + 1e-3f;
             // pixel centres relative to the Gaussian centre
             const float ox = (float)(tg.x0 - tg.rx) + 0.5f - ux;
@@ -147,8 +151,10 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
                 const int bx = (sb % SB) * 8, by = (sb / SB) * 8;
                 const float X0 = ox + (float)max(xl, bx), X1 = ox + (float)min(xh, bx + 7);
                 const float Y0 = oy + (float)max(yl, by), Y1 = oy + (float)min(yh, by + 7);
-                if (box_min_exponent(ra.z, ra.w, rb.x, X0, X1, Y0, Y1) > thr) m &= ~(1u << sb);
+                if (box_min_exponent(ra.z, ra.w, rb.x, X0, X1, Y0, Y1) > thr) mc &= ~(1u << sb);
             }
+            if (CULL) m = mc;
+            if (DUAL) s_cmask[k] = (uint16_t)mc;
         }
         s_mask[k] = (uint16_t)m;
         if (s_rid) s_rid[k] = (uint32_t)rid;
@@ -181,8 +187,9 @@ __device__ __forceinline__ float4 slot16(const float4 *base, uint32_t off) {
 }
 
 // LDS of one blending workgroup (the forward leaves rid and wmax unused;
-// c holds the staged RGB colours of the CH = 3 forward).
-template <int T, int B, int CH = 1>
+// c holds the staged RGB colours of the CH = 3 forward, cmask the culled
+// sub-block masks of the counting forward).
+template <int T, int B, int CH = 1, bool CNT = false>
 struct BlendLds {
     static constexpr int NW = T * T / kWave;
     float4 a[B];
@@ -190,6 +197,7 @@ struct BlendLds {
     float4 c[CH == 3 ? B : 1];
     uint32_t rid[B];
     uint16_t mask[B];
+    uint16_t cmask[CNT ? B : 1];
     alignas(16) uint16_t list[NW][B];
     int wmax[NW];
     int next;
@@ -198,11 +206,16 @@ struct BlendLds {
 // CH = 1: the radiative intensity of the record (Eq. 10).  CH = 3: the
 // three colour channels of the record's fourth slot (the comparison model),
 // image planar [3][total pixels]; the blending decisions are the same.
+// COUNT: the work counts of xg_render_counts (rows documented there)
+// instead of the image.  The walk then covers every list entry whose
+// rectangle touches the wavefront's 8 x 8 block (the definition's
+// evaluations); the culled mask tells which of them the blending kernels
+// visit.
 template <int T, int B, bool COUNT, bool STORE, int CH = 1>
 __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera *cams,
                                          const Params &p, float *image, float *final_t,
                                          int32_t *n_contrib, int32_t *counts, const TStore &ts,
-                                         const L1Fuse &l1, BlendLds<T, B, CH> &sh) {
+                                         const L1Fuse &l1, BlendLds<T, B, CH, COUNT> &sh) {
     static_assert(CH == 1 || (CH == 3 && !COUNT && !STORE), "RGB forward: plain variant only");
     static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
     constexpr int NT = T * T;
@@ -230,7 +243,9 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
 
     float Tr = 1.0f, C = 0.0f, Cg = 0.0f, Cb = 0.0f;
     int last = 0;
-    int n_eval = 0, n_con = 0, n_upto = 0;
+    // counting variant: per lane (rows 0-2, 6, 7) and per wavefront (3-5)
+    int n_eval = 0, n_con = 0, n_upto = 0, n_fev = 0, n_bev = 0, bev_run = 0;
+    int w_red = 0, w_bvis = 0, w_fvis = 0, w_cvis = 0;
     bool done = !inside;
     int nc = 0;   // contributors so far (stored variant)
     float *tbase = STORE ? ts.t + (int64_t)tile * ts.slots * NT + threadIdx.x : nullptr;
@@ -239,8 +254,8 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         if (!__syncthreads_or(!done)) break;
         // the counting variant keeps every rectangle evaluation (the work
         // count of the definition), the others skip sub-blocks out of reach
-        stage<T, NT, !COUNT>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr,
-                             CH == 3 ? sh.c : nullptr);
+        stage<T, NT, !COUNT, COUNT>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr,
+                                    CH == 3 ? sh.c : nullptr, COUNT ? sh.cmask : nullptr);
         __syncthreads();
         if (!__any(!done)) continue;
         const int nl = wave_list(s_mask, cnt, w, list);
@@ -262,7 +277,9 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             const uint32_t rect = __float_as_uint(sb.w);
             const int rxl = rect & 255, rxh = (rect >> 8) & 255;
             const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            const bool act = !done && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const bool inr = lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const bool act = !done && inr;
+            const bool live = COUNT && __any(!done);   // before this entry
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
             const bool con = act && ev.alpha >= amin;
             const float Tn = fmaf(-Tr, ev.alpha, Tr);   // T (1 - alpha), one rounding
@@ -287,6 +304,18 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
                 n_eval += act ? 1 : 0;
                 n_con += keep ? 1 : 0;
                 n_upto = keep ? n_eval : n_upto;
+                const bool any_keep = __any(keep);
+                w_red += any_keep ? 1 : 0;
+                if ((sh.cmask[off >> 4] >> w) & 1u) {   // an entry the blend kernels visit
+                    ++w_cvis;
+                    if (live) {
+                        ++w_fvis;
+                        n_fev += act ? 1 : 0;
+                    }
+                    bev_run += inr ? 1 : 0;
+                    if (any_keep) w_bvis = w_cvis;
+                    n_bev = keep ? bev_run : n_bev;
+                }
             }
           }
           if (!__any(!done)) break;
@@ -297,9 +326,16 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     if (inside) {
         const int64_t o = (int64_t)tg.pix_off + (int64_t)py * tg.W + px;
         if (COUNT) {
+            const int64_t tp = ws.total_pixels;
+            const bool first = lane == 0;   // the block's first pixel
             counts[o] = n_eval;
-            counts[ws.total_pixels + o] = n_con;
-            counts[2 * ws.total_pixels + o] = n_upto;
+            counts[tp + o] = n_con;
+            counts[2 * tp + o] = n_upto;
+            counts[3 * tp + o] = first ? w_red : 0;
+            counts[4 * tp + o] = first ? w_bvis : 0;
+            counts[5 * tp + o] = first ? w_fvis : 0;
+            counts[6 * tp + o] = n_fev;
+            counts[7 * tp + o] = n_bev;
         } else {
             image[o] = C;
             if constexpr (CH == 3) {
@@ -317,8 +353,8 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
 }
 
 // Pops the next tile of the heavy-first work order (-1 when exhausted).
-template <int T, int B>
-__device__ __forceinline__ int pop_tile(const Ws &ws, int32_t *queue, BlendLds<T, B> &sh) {
+template <typename Lds>
+__device__ __forceinline__ int pop_tile(const Ws &ws, int32_t *queue, Lds &sh) {
     if (threadIdx.x == 0) {
         const int q = atomicAdd(queue, 1);
         sh.next = q < ws.total_tiles ? ws.tile_order[q] : -1;
@@ -353,14 +389,14 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *ca
                                                       float *image, float *final_t,
                                                       int32_t *n_contrib, int32_t *counts,
                                                       TStore ts, L1Fuse l1) {
-    __shared__ BlendLds<T, B> sh;
+    __shared__ BlendLds<T, B, 1, COUNT> sh;
     if (!PERSIST) {
         fwd_tile<T, B, COUNT, STORE>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
                                      final_t, n_contrib, counts, ts, l1, sh);
         return;
     }
     for (;;) {
-        const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_fwd, sh);
+        const int tile = pop_tile(ws, &ws.hdr->queue_fwd, sh);
         if (tile < 0) break;
         fwd_tile<T, B, COUNT, false>(tile, ws, cams, p, image, final_t, n_contrib, counts, ts, l1, sh);
     }
@@ -579,7 +615,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *ca
         return;
     }
     for (;;) {
-        const int tile = pop_tile<T, B>(ws, &ws.hdr->queue_bwd, sh);
+        const int tile = pop_tile(ws, &ws.hdr->queue_bwd, sh);
         if (tile < 0) break;
         bwd_tile<T, B, false>(tile, ws, cams, p, dl_dimage, final_t, n_contrib, ts, sh);
         __syncthreads();

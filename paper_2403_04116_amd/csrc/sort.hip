@@ -491,6 +491,30 @@ __global__ __launch_bounds__(1024) void k_tile_order(Ws ws) {
     }
 }
 
+// 64-bit sort keys of the sorted pairs, for inspection: keys[p] =
+// (global tile id << 32) | float32 bits of the camera depth of (view of the
+// tile, Gaussian), vals[p] = Gaussian index, for p below the device pair
+// count (nothing when the status word is not XG_OK).  Grid-stride over at
+// most `cap` pairs.
+__global__ __launch_bounds__(256) void k_pair_keys(Ws ws, const xg_camera *cams, uint64_t *keys,
+                                                   uint32_t *vals, int64_t cap) {
+    const WsHeader *h = ws.hdr;
+    const int64_t np = h->n_pairs;
+    int64_t n = (h->status != XG_OK || np > ws.cap) ? 0 : np;
+    if (n > cap) n = cap;
+    const uint32_t *tiles = ws.ptile[ws.pair_sel];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t word = tiles[p];
+        const uint32_t tile = ws.pair_gbits ? word >> ws.pair_gbits : word;
+        const uint32_t gi = ws.pair_gbits ? (word & ws.pair_gmask) : ws.pval[ws.pair_sel][p];
+        const int view = view_of_tile(cams, ws.n_views, (int)tile);
+        const uint32_t depth = __float_as_uint(ws.rec[(int64_t)view * ws.n + gi].b.w);
+        keys[p] = ((uint64_t)tile << 32) | depth;
+        vals[p] = gi;
+    }
+}
+
 template <class S>
 hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s) {
     const unsigned nb = (unsigned)(blocks > 0 ? blocks : 1);
@@ -525,6 +549,16 @@ hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s) {
 
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_keys(const Ws &ws, const xg_camera *cams, uint64_t *keys, uint32_t *vals,
+                            int64_t cap, hipStream_t s) {
+    int64_t nb = (cap < ws.cap ? cap : ws.cap);
+    nb = (nb + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_pair_keys, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, ws, cams, keys,
+                       vals, cap);
     return hipGetLastError();
 }
 

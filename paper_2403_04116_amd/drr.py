@@ -99,6 +99,12 @@ class Frame:
         self.n_views = len(cams)
         self.sizes = [(c.width, c.height) for c in cams]
         self.capacity = int(pair_capacity) if pair_capacity else max(1 << 16, 6 * self.n * self.n_views)
+        # bumped by every preprocess: a backward checks that the lists it walks
+        # are those of its own forward
+        self.generation = 0
+        # whether a backward has added into the 2-D gradient accumulators since
+        # the last preprocess (which clears them)
+        self.accumulated = False
         self._allocate()
 
     # -- workspace -----------------------------------------------------------
@@ -135,28 +141,19 @@ class Frame:
     def n_pairs(self) -> int:
         return int(self.ws_tensor(self.layout.n_pairs, torch.int32, 1).item())
 
-    def sorted_pairs(self):
+    def sorted_pairs(self, stream=None):
         """(keys, values, ranges) of the sorted lists, for inspection
-        (synchronises).  keys[p] = tile << 32 | depth bits, rebuilt from the
-        stored tile ids and the render records' depth words."""
+        (synchronises): keys[p] = tile << 32 | depth bits and values[p] =
+        Gaussian index as written by xg_pair_keys."""
         p = self.n_pairs()
         if self.status() != X.XG_OK:
             p = 0
-        b = int(self.layout.pair_index_bits)
-        raw = self.ws_tensor(self.layout.pair_tiles, torch.int32, p).long() & 0xFFFFFFFF
-        if b:   # packed: tile << b | Gaussian index in one word
-            tiles = raw >> b
-            vals = (raw & ((1 << b) - 1)).to(torch.int32)
-        else:
-            tiles = raw
-            vals = self.ws_tensor(self.layout.pair_values, torch.int32, p)
+        keys = torch.empty(max(p, 1), dtype=torch.int64, device=self.device)
+        vals = torch.empty(max(p, 1), dtype=torch.int32, device=self.device)
+        X.xg_pair_keys(self.frame, keys.data_ptr(), vals.data_ptr(), p, _stream(stream))
+        torch.cuda.synchronize(self.device)
         ranges = self.ws_tensor(self.layout.ranges, torch.int32, 2 * self.total_tiles)
-        toff = torch.tensor([c.tile_offset for c in self.cams], dtype=torch.int64, device=self.device)
-        view = torch.searchsorted(toff, tiles, right=True) - 1
-        rec = self.ws_tensor(self.layout.records, torch.int32, 16 * self.n * self.n_views)
-        depth = rec.view(-1, 16)[view * self.n + vals.long(), 7].long() & 0xFFFFFFFF
-        keys = (tiles << 32) | depth
-        return keys, vals, ranges.view(self.total_tiles, 2)
+        return keys[:p], vals[:p], ranges.view(self.total_tiles, 2)
 
     # -- stages --------------------------------------------------------------
     def preprocess_sort(self, g: dict, stream=None) -> None:
@@ -164,6 +161,15 @@ class Frame:
         s = _stream(stream)
         X.xg_preprocess(self.frame, gs, s)
         X.xg_bin_sort(self.frame, s)
+        self.generation += 1
+        self.accumulated = False
+
+    def clear_2d_grads(self) -> None:
+        """Zeroes the per-(view, Gaussian) 2-D gradient accumulators (what the
+        preprocess does), so that a second backward of the same forward does
+        not add to the first one's sums."""
+        self.ws_tensor(self.layout.grad2d, torch.float32, 8 * self.n * self.n_views).zero_()
+        self.accumulated = False
 
     def fit_capacity(self, g: dict, headroom: float = 1.25) -> int:
         """Runs preprocess + sort, grows the workspace if the pairs did not fit
@@ -219,13 +225,16 @@ class Frame:
 
     def backward(self, g: dict, dl_dimage: torch.Tensor, final_t: torch.Tensor,
                  n_contrib: torch.Tensor, grads: dict | None = None, stream=None) -> dict:
-        """Adjoint of forward(); once per forward (the 2-D accumulators are
-        cleared by the preprocess)."""
+        """Adjoint of forward() (xg_render_bwd), added to ``grads`` (new
+        zeroed tensors if None).  A repeated backward of the same forward
+        clears the 2-D accumulators first."""
         grads = self.new_grads(g) if grads is None else grads
         gr = X.XgGrads(*(grads[k].data_ptr() for k in PARAMS))
-        s = _stream(stream)
-        X.xg_render_bwd(self.frame, dl_dimage.data_ptr(), final_t.data_ptr(), n_contrib.data_ptr(), s)
-        X.xg_preprocess_bwd(self.frame, gaussians_struct(g), gr, s)
+        if self.accumulated:
+            self.clear_2d_grads()
+        X.xg_render_bwd(self.frame, gaussians_struct(g), dl_dimage.data_ptr(), final_t.data_ptr(),
+                        n_contrib.data_ptr(), gr, _stream(stream))
+        self.accumulated = True
         return grads
 
     # -- stored-transmittance variant ------------------------------------------
@@ -249,17 +258,21 @@ class Frame:
                        stream=None) -> dict:
         grads = self.new_grads(g) if grads is None else grads
         gr = X.XgGrads(*(grads[k].data_ptr() for k in PARAMS))
-        s = _stream(stream)
-        X.xg_render_bwd_store(self.frame, dl_dimage.data_ptr(), final_t.data_ptr(),
-                              n_contrib.data_ptr(), store.view.data_ptr(), store.slots,
-                              store.view.numel(), s)
-        X.xg_preprocess_bwd(self.frame, gaussians_struct(g), gr, s)
+        if self.accumulated:
+            self.clear_2d_grads()
+        X.xg_render_bwd_store(self.frame, gaussians_struct(g), dl_dimage.data_ptr(),
+                              final_t.data_ptr(), n_contrib.data_ptr(), store.view.data_ptr(),
+                              store.slots, store.view.numel(), gr, _stream(stream))
+        self.accumulated = True
         return grads
 
     def render_counts(self, stream=None) -> torch.Tensor:
-        """Per-pixel [evaluations, contributors, evaluations up to the last
-        contributor] of the current sorted lists (int32 [3, pixels])."""
-        out = torch.empty((3, self.total_pixels), dtype=torch.int32, device=self.device)
+        """Work counts of the current sorted lists (int32 [XG_COUNT_ROWS,
+        pixels], rows as documented at xg_render_counts): per-pixel
+        evaluations, contributors, revisited evaluations; per 8 x 8 block the
+        backward's wavefront reductions and the entries the backward and the
+        forward visit; per-pixel evaluations inside those visits."""
+        out = torch.empty((X.COUNT_ROWS, self.total_pixels), dtype=torch.int32, device=self.device)
         X.xg_render_counts(self.frame, out.data_ptr(), _stream(stream))
         return out
 
@@ -306,15 +319,24 @@ class DRRFunction(torch.autograd.Function):
     """I = F_DRR(M_ext, M_int, {G_i}) (Eq. 5) with the hand-written backward.
 
     Saves only the final transmittance and the last contributor per pixel;
-    the backward recomputes the transmittance by division.
+    the backward recomputes the transmittance by division.  The sorted lists
+    stay in the frame's workspace between forward and backward, so the
+    backward must come before the frame renders again (checked: RuntimeError
+    otherwise).  The forward reads the device status word (one
+    synchronisation): on a pair overflow it grows the workspace and renders
+    again; any other failure raises XgError.  A second backward of the same
+    forward (retain_graph) gives the same gradients again.
     """
 
     @staticmethod
     def forward(ctx, means, scales, quats, opacity, intensity, frame: Frame):
-        g = {"means": means.contiguous(), "scales": scales.contiguous(), "quats": quats.contiguous(),
-             "opacity": opacity.contiguous(), "intensity": intensity.contiguous()}
-        image, final_t, n_contrib = frame.forward(g)
+        g = {"means": means.detach().contiguous(), "scales": scales.detach().contiguous(),
+             "quats": quats.detach().contiguous(), "opacity": opacity.detach().contiguous(),
+             "intensity": intensity.detach().contiguous()}
+        frame.fit_capacity(g)          # preprocess + lists; grows the workspace on overflow
+        image, final_t, n_contrib = frame.render_fwd(g)
         ctx.frame = frame
+        ctx.generation = frame.generation
         ctx.save_for_backward(g["means"], g["scales"], g["quats"], g["opacity"], g["intensity"],
                               final_t, n_contrib)
         ctx.mark_non_differentiable(final_t, n_contrib)
@@ -322,10 +344,14 @@ class DRRFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, dl_dimage, _dt, _dn):
+        frame = ctx.frame
+        if frame.generation != ctx.generation:
+            raise RuntimeError("DRRFunction.backward: the frame rendered again after this forward; "
+                               "its sorted lists belong to the later render")
         means, scales, quats, opacity, intensity, final_t, n_contrib = ctx.saved_tensors
         g = {"means": means, "scales": scales, "quats": quats, "opacity": opacity,
              "intensity": intensity}
-        grads = ctx.frame.backward(g, dl_dimage.contiguous(), final_t, n_contrib)
+        grads = frame.backward(g, dl_dimage.contiguous(), final_t, n_contrib)
         return (grads["means"], grads["scales"], grads["quats"], grads["opacity"],
                 grads["intensity"], None)
 

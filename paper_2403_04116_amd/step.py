@@ -61,13 +61,15 @@ class TrainStep:
                                   st.view.numel(), s)
             X.xg_l1_grad(self.image.data_ptr(), self.target.data_ptr(), self.dl.data_ptr(),
                          self.image.numel(), self.scale, s)
+        # the 2-D stage, then the projection adjoint writing (or adding) the
+        # parameter gradients
         if st is None:
-            X.xg_render_bwd(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
-                            self.n_contrib.data_ptr(), s)
+            X.xg_render_bwd_2d(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
+                               self.n_contrib.data_ptr(), s)
         else:
-            X.xg_render_bwd_store(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
-                                  self.n_contrib.data_ptr(), st.view.data_ptr(), st.slots,
-                                  st.view.numel(), s)
+            X.xg_render_bwd_store_2d(f.frame, self.dl.data_ptr(), self.final_t.data_ptr(),
+                                     self.n_contrib.data_ptr(), st.view.data_ptr(), st.slots,
+                                     st.view.numel(), s)
         if self.zero_grads:
             X.xg_preprocess_bwd_write(f.frame, gs, gr, s)   # this step's gradients only
         else:

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_status_strings():
-    assert P.xg_abi_version() == 3
+    assert P.xg_abi_version() == 4
     for st in (0, 1, 2, 3):
         assert X.status_string(st).startswith("XG_")
 
@@ -218,7 +218,11 @@ def test_store_size_and_validation():
             X.xg_render_fwd_store(f, g, 256, 256, 256, store, slots, nbytes, 0)
         assert e.value.status == X.XG_EINVAL
         with pytest.raises(X.XgError) as e:
-            X.xg_render_bwd_store(f, 256, 256, 256, store, slots, nbytes, 0)
+            X.xg_render_bwd_store_2d(f, 256, 256, 256, store, slots, nbytes, 0)
+        assert e.value.status == X.XG_EINVAL
+        with pytest.raises(X.XgError) as e:
+            X.xg_render_bwd_store(f, g, 256, 256, 256, store, slots, nbytes,
+                                  X.XgGrads(256, 256, 256, 256, 256), 0)
         assert e.value.status == X.XG_EINVAL
     f.settings.flags = 1           # the persistent queue has no stored variant
     with pytest.raises(X.XgError) as e:
@@ -300,3 +304,44 @@ def test_pair_packing_decision():
     assert lay.pair_index_bits == 0 and lay.pair_values != lay.pair_tiles
     one, _ = _frame(n=1, views=((64, 64),))
     assert P.xg_ws_layout_of(one).pair_index_bits == 1
+
+
+def test_render_bwd_validation():
+    """The one-call backward (2-D stage + projection adjoint) checks all its
+    arguments before enqueueing either stage."""
+    f, _ = _frame()
+    need = P.xg_workspace_size(f)
+    f.cams_dev, f.ws, f.ws_bytes = 256, 512, need
+    g = X.XgGaussians(4096, 4096, 4096, 4096, 4096, 100)
+    gr = X.XgGrads(4096, 4096, 4096, 4096, 4096)
+    bad = [(g, 0, 4096, 4096, gr), (g, 4096, 0, 4096, gr), (g, 4096, 4096, 0, gr),
+           (g, 4096, 4096, 4096, X.XgGrads(4096, 0, 4096, 4096, 4096)),
+           (X.XgGaussians(4096, 4096, 4096, 4096, 4096, 99), 4096, 4096, 4096, gr)]
+    for gg, dl, ft, nc, grads in bad:
+        with pytest.raises(X.XgError) as e:
+            X.xg_render_bwd(f, gg, dl, ft, nc, grads)
+        assert e.value.status == X.XG_EINVAL
+
+
+def test_ws_inspect_matches_layout():
+    """xg_ws_inspect returns the workspace addresses the layout describes
+    (host arithmetic only: the workspace pointer is never dereferenced)."""
+    f, _ = _frame(views=((64, 64), (40, 24)))
+    lay = P.xg_ws_layout_of(f)
+    base = 1 << 20
+    f.cams_dev, f.ws, f.ws_bytes = 256, base, lay.total
+    v = X.xg_ws_inspect(f)
+    assert v.status == base + lay.status and v.n_pairs == base + lay.n_pairs
+    assert v.pair_tiles == base + lay.pair_tiles and v.pair_values == base + lay.pair_values
+    assert v.ranges == base + lay.ranges and v.records == base + lay.records
+    assert v.grad2d == base + lay.grad2d and v.pair_index_bits == lay.pair_index_bits
+    assert v.total_tiles == 16 + 3 * 2 and v.total_pixels == 64 * 64 + 40 * 24
+    f.ws = 0
+    with pytest.raises(X.XgError):
+        X.xg_ws_inspect(f)
+    for keys, vals, cap in ((0, 4096, 10), (4096, 0, 10), (4096, 4096, -1)):
+        f.ws = base
+        with pytest.raises(X.XgError) as e:
+            X.xg_pair_keys(f, keys, vals, cap)
+        assert e.value.status == X.XG_EINVAL
+

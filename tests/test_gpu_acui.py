@@ -11,7 +11,7 @@ import pytest
 import oracle as O
 import scenes as S
 from oracle import acui
-from _gpu import compare_forward, gpu_run, note, oracle_cams, oracle_run
+from _gpu import compare_forward, compare_pixels, gpu_run, note, oracle_cams, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_acui_reduced_scan_forward():
     gpu = gpu_run(g_gpu, angles, sizes, backward=False)
     ref = oracle_run(g_ref, angles, sizes)
     assert gpu["status"] == 0
-    compare_forward(gpu, ref)
+    compare_forward(gpu, ref, label="acui reduced scan")
 
 
 def test_acui_full_scan_keys_and_sampled_pixels():
@@ -83,10 +83,6 @@ def test_acui_full_scan_keys_and_sampled_pixels():
         # 8 anywhere, 8 in the central quarter (inside the object's projection)
         cx, cy = c.width // 4 + rng.integers(0, c.width // 2, 8), c.height // 4 + rng.integers(0, c.height // 2, 8)
         pix = np.concatenate([rng.choice(npx, 8, replace=False), cy * c.width + cx]).astype(np.int32)
-        r = O.render_brute(g_ref, c, st, pix)
-        ok = r["flags"] == 0
-        err = np.abs(gpu["image"][off + pix].astype(np.float64) - r["image"])[ok]
-        assert err.max(initial=0) <= 1e-5, (v, err.max())
-        terr = np.abs(gpu["final_t"][off + pix].astype(np.float64) - r["final_t"])[ok]
-        assert terr.max(initial=0) <= 1e-5, (v, terr.max())
+        compare_pixels(gpu["image"][off + pix], gpu["final_t"][off + pix], g_ref, c, st, pix,
+                       label=f"acui view {v}")
         off += npx

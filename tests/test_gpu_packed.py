@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import scenes as S
-from _gpu import IMG_TOL, gpu_run, note, oracle_cams
+from _gpu import compare_pixels, gpu_run, note, oracle_cams
 
 pytestmark = pytest.mark.gpu
 
@@ -37,8 +37,6 @@ def test_packed_pairs_fill_the_word():
     for v, c in enumerate(cams[:3]):
         npx = c.width * c.height
         pix = rng.choice(npx, 32, replace=False).astype(np.int32)
-        r = O.render_brute(g, c, st, pix)
-        ok = r["flags"] == 0
-        err = np.abs(gpu["image"][off + pix].astype(np.float64) - r["image"])[ok]
-        assert err.max(initial=0) <= IMG_TOL, (v, err.max())
+        compare_pixels(gpu["image"][off + pix], gpu["final_t"][off + pix], g, c, st, pix,
+                       label=f"packed view {v}")
         off += npx

@@ -17,7 +17,8 @@ import pytest
 
 import oracle as O
 import scenes as S
-from _gpu import FLAG_FRAC, GRAD_TOL, IMG_TOL, KEYS, gpu_run, note, oracle_cams
+from _gpu import (GRAD_TOL, KEYS, add_branches, compare_forward, gpu_run, grad_upstream, note,
+                  oracle_cams)
 
 pytestmark = pytest.mark.gpu
 
@@ -49,13 +50,10 @@ def _check_views(c, views, grad_gaussians):
         np.testing.assert_array_equal(gpu["keys"][m], okeys)
         np.testing.assert_array_equal(gpu["values"][m], pr["values"])
         r = O.render_binned(g, cam, st, pr["values"], pr["ranges"])
-        ok = r["flags"] == 0
-        assert (~ok).mean() <= FLAG_FRAC
-        err = np.abs(gpu["image"][sl[v]].astype(np.float64) - r["image"])[ok]
-        terr = np.abs(gpu["final_t"][sl[v]].astype(np.float64) - r["final_t"])[ok]
-        assert err.max(initial=0) <= IMG_TOL and terr.max(initial=0) <= IMG_TOL, (v, err.max(), terr.max())
-        np.testing.assert_array_equal(gpu["n_contrib"][sl[v]][ok], r["n_contrib"][ok])
-        note(f"workload{c}: view {v}: {int(m.sum())} pairs bit-exact, image max err {err.max():.2e}")
+        add_branches(r, g, cam, st, pr["values"], pr["ranges"])
+        mt = compare_forward({k: gpu[k][sl[v]] for k in ("image", "final_t", "n_contrib")}, r,
+                             check_keys=False, label=f"workload{c} view {v}")
+        note(f"workload{c}: view {v}: {int(m.sum())} pairs bit-exact, image max err {mt.err:.2e}")
     del gpu, frame
     # gradients on a frame of the sampled views
     angles = [w.angles[v] for v in views]
@@ -64,15 +62,19 @@ def _check_views(c, views, grad_gaussians):
     note(f"workload{c}: oracle forward of the sampled views")
     pr = O.pairs(g, ref["cams"], st)
     r = O.render_binned(g, ref["cams"], st, pr["values"], pr["ranges"])
+    add_branches(r, g, ref["cams"], st, pr["values"], pr["ranges"])
     npx = sum(a * b for a, b in sizes)
     up = np.random.default_rng(1000 * c + 3).normal(size=npx).astype(np.float32)
-    up = np.where(r["flags"] == 0, up, 0).astype(np.float32) / npx
+    up = (grad_upstream(up, r) / npx).astype(np.float32)
     note(f"workload{c}: gpu forward + backward of the sampled views")
-    gg = gpu_run(g, angles, sizes, tile=16, lds=256, upstream=up)["grads"]
+    run = gpu_run(g, angles, sizes, tile=16, lds=256, upstream=up)
+    gg = run["grads"]
+    mt = compare_forward(run, {**r, "pairs": pr}, check_keys=False, label=f"workload{c} sampled views")
     sel = np.zeros(w.n, bool)
     sel[np.random.default_rng(1000 * c + 4).choice(w.n, grad_gaussians, replace=False)] = True
     note(f"workload{c}: oracle adjoint of {grad_gaussians} sampled Gaussians")
-    rg = O.backward(g, ref["cams"], st, up, binned=(pr["values"], pr["ranges"]), sel=sel)
+    rg = O.backward(g, ref["cams"], st, up, binned=(pr["values"], pr["ranges"]), sel=sel,
+                    flip=mt.flip)
     for k in KEYS:
         a = gg[k][sel].astype(np.float64).reshape(-1)
         b = rg[k][sel].reshape(-1)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import scenes as S
-from _gpu import KEYS, compare_grads, note, oracle_run
+from _gpu import KEYS, compare_forward, compare_grads, grad_upstream, note, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -41,12 +41,14 @@ def _check(g, angles, sizes, slots, tile=16, lds=256, seed=3):
     ref = oracle_run(g, angles, sizes, tile=tile)
     npx = sum(w * h for w, h in sizes)
     up = np.random.default_rng(seed).normal(size=npx).astype(np.float32)
-    up = np.where(ref["flags"] == 0, up, 0).astype(np.float32)
+    up = grad_upstream(up, ref)
     fa, ga, fb, gb, store, frame = _both(g, angles, sizes, slots, up, tile, lds)
     for x, y in zip(fa, fb):
         np.testing.assert_array_equal(x, y)
+    m = compare_forward({"image": fb[0], "final_t": fb[1], "n_contrib": fb[2]}, ref,
+                        check_keys=False, label=f"stored slots={slots}")
     rg = O.backward(g, ref["cams"], ref["st"], up, binned=(ref["pairs"]["values"],
-                                                          ref["pairs"]["ranges"]))
+                                                          ref["pairs"]["ranges"]), flip=m.flip)
     errs = compare_grads(gb, rg)
     # stored and divided transmittances agree to float32 rounding
     for k in KEYS:
