@@ -29,7 +29,7 @@ struct Eval {
 };
 
 // alpha of one staged Gaussian at a pixel centre (px, py), both relative
-// to the block reference point.  sa = (ux, uy, qa, qb), sb = (qc, o, intensity, rect).
+// to the block reference point.  sa = (ux, uy, qa, qb), sb = (qc, o, intensity, rectangle word).
 __device__ __forceinline__ Eval splat_eval(const float4 &sa, const float4 &sb, float px, float py,
                                            float amax) {
 #pragma clang fp contract(off)
@@ -65,6 +65,39 @@ __device__ __forceinline__ TileGeom tile_geom(const xg_camera *cams, int n_views
     t.rx = (t.x0 & ~31) + 16;
     t.ry = (t.y0 & ~31) + 16;
     return t;
+}
+
+// The tile-local rectangle [xl, xh] x [yl, yh] of a staged entry, in the
+// form the blend loops test it.  T <= 16: bit x of the low half and bit y of
+// the high half are set for the columns and rows the rectangle covers, and a
+// lane at (lx, ly) is inside iff both of its two bits are set: one AND and
+// one compare per entry against a per-lane constant.  T = 32 (32 columns do
+// not fit a half word): the four bounds as bytes, compared one by one.
+template <int T>
+__device__ __forceinline__ uint32_t rect_word(int xl, int xh, int yl, int yh) {
+    if constexpr (T <= 16) {
+        const uint32_t xm = ((2u << xh) - 1u) & ~((1u << xl) - 1u);
+        const uint32_t ym = ((2u << yh) - 1u) & ~((1u << yl) - 1u);
+        return xm | (ym << 16);
+    } else {
+        return (uint32_t)xl | ((uint32_t)xh << 8) | ((uint32_t)yl << 16) | ((uint32_t)yh << 24);
+    }
+}
+
+template <int T>
+__device__ __forceinline__ uint32_t rect_lane_key(int lx, int ly) {
+    return T <= 16 ? (1u << lx) | (1u << (16 + ly)) : 0u;
+}
+
+template <int T>
+__device__ __forceinline__ bool in_rect(uint32_t rect, uint32_t key, int lx, int ly) {
+    if constexpr (T <= 16) {
+        return (rect & key) == key;
+    } else {
+        const int rxl = rect & 255, rxh = (rect >> 8) & 255;
+        const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
+        return lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+    }
 }
 
 // Bit s of the result: the tile-local rectangle [xl, xh] x [yl, yh] touches
@@ -135,7 +168,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         const float uy = (float)(rc.y - tg.ry) + ra.y;
         const int xl = max((rc.z & 0xffff) - tg.x0, 0), xh = min((rc.z >> 16) - tg.x0, T - 1);
         const int yl = max((rc.w & 0xffff) - tg.y0, 0), yh = min((rc.w >> 16) - tg.y0, T - 1);
-        const uint32_t rect = (uint32_t)xl | ((uint32_t)xh << 8) | ((uint32_t)yl << 16) | ((uint32_t)yh << 24);
+        const uint32_t rect = rect_word<T>(xl, xh, yl, yh);
         s_a[k] = make_float4(ux, uy, ra.z, ra.w);
         s_b[k] = make_float4(rb.x, rb.y, rb.z, __uint_as_float(rect));
         uint32_t m = subblock_mask<SB>(xl, xh, yl, yh);
@@ -234,6 +267,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     const bool inside = px < tg.W && py < tg.H;
     const float pxr = (float)(px - tg.rx) + 0.5f;
     const float pyr = (float)(py - tg.ry) + 0.5f;
+    const uint32_t rkey = rect_lane_key<T>(lx, ly);
 
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
     const uint32_t e = ws.ranges[2 * (int64_t)tile + 1];
@@ -274,10 +308,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
             const uint32_t off = (iw[u >> 1] >> (16 * (u & 1))) & 0xffffu;   // 16 x batch index
             const float4 sa = slot16(s_a, off);
             const float4 sb = slot16(s_b, off);
-            const uint32_t rect = __float_as_uint(sb.w);
-            const int rxl = rect & 255, rxh = (rect >> 8) & 255;
-            const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            const bool inr = lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const bool inr = in_rect<T>(__float_as_uint(sb.w), rkey, lx, ly);
             const bool act = !done && inr;
             const bool live = COUNT && __any(!done);   // before this entry
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
@@ -485,6 +516,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     const bool inside = px < tg.W && py < tg.H;
     const float pxr = (float)(px - tg.rx) + 0.5f;
     const float pyr = (float)(py - tg.ry) + 0.5f;
+    const uint32_t rkey = rect_lane_key<T>(lx, ly);
 
     const uint32_t s = ws.ranges[2 * (int64_t)tile];
     const uint32_t *vals = ws.pair_vals;
@@ -558,10 +590,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                 sb_n = slot16(s_b, off_n);
             }
             if (j0 + u >= nl) continue;
-            const uint32_t rect = __float_as_uint(sb.w);
-            const int rxl = rect & 255, rxh = (rect >> 8) & 255;
-            const int ryl = (rect >> 16) & 255, ryh = rect >> 24;
-            const bool inr = (int)off <= lastk16 && lx >= rxl && lx <= rxh && ly >= ryl && ly <= ryh;
+            const bool inr = (int)off <= lastk16 && in_rect<T>(__float_as_uint(sb.w), rkey, lx, ly);
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
             const bool act = inr && ev.alpha >= amin;
             if (!__any(act)) continue;
