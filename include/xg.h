@@ -444,6 +444,27 @@ xg_status xg_acui_grid(const double size[3], const int32_t grid[3], double d, fl
 xg_status xg_loss_grad(const xg_frame *f /* [host] */, const float *image, const float *target,
                        float gamma, float *dl_dimage, float *loss, void *stream);
 
+/* Allocation-free form of xg_loss_grad, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * xg_loss_grad, but the three per-pixel maps and the per-strip loss shares
+ * live in a static device array of XG_STATIC_SCRATCH_BYTES held by the
+ * library (one copy per device, resident until the process ends) instead
+ * of the frame's workspace: f->ws and f->ws_bytes are not read (may be
+ * NULL / 0); f->cams and f->cams_dev are.  Allocates and frees nothing;
+ * the first call on a device resolves that device's address of the array
+ * (the current device must be the one `stream` belongs to).  Every value
+ * read from the array is written earlier in the same call, so nothing is
+ * cleared.  All calls on one device share the array: calls that overlap
+ * in time on one device (different streams, or host threads) race and
+ * give undefined results; calls in order on one stream are safe.
+ * XG_ECAPACITY (synchronous, nothing enqueued) when 12 * total pixels +
+ * 4 * ceil(W / 48) * ceil(H / 8) summed over views exceeds
+ * XG_STATIC_SCRATCH_BYTES (e.g. 8 views of 512 x 512 need 25.2 MB). */
+#define XG_STATIC_SCRATCH_BYTES (32u << 20)
+xg_status xg_loss_grad_static(const xg_frame *f /* [host] */, const float *image, const float *target,
+                              float gamma, float *dl_dimage, float *loss, void *stream);
+
 /* L1 term of Eq. 11: dl_dimage[p] = scale * sign(image[p] - target[p])
  * (0 where equal), for n_pixels pixels. */
 xg_status xg_l1_grad(const float *image, const float *target, float *dl_dimage,

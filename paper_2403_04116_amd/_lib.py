@@ -167,6 +167,8 @@ _L.xg_acui_grid.restype = _S
 _L.xg_acui_grid.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_double, _P, C.c_int64, _P]
 _L.xg_loss_grad.restype = _S
 _L.xg_loss_grad.argtypes = [C.POINTER(XgFrame), _P, _P, C.c_float, _P, _P, _P]
+_L.xg_loss_grad_static.restype = _S
+_L.xg_loss_grad_static.argtypes = [C.POINTER(XgFrame), _P, _P, C.c_float, _P, _P, _P]
 _L.xg_l1_grad.restype = _S
 _L.xg_l1_grad.argtypes = [_P, _P, _P, C.c_int64, C.c_float, _P]
 
@@ -180,7 +182,8 @@ EXPORTED = ("xg_abi_version", "xg_status_string", "xg_default_settings", "xg_cam
             "xg_render_fwd_store", "xg_render_bwd_store", "xg_rirf_fwd", "xg_rirf_bwd",
             "xg_loss_grad", "xg_acui_count", "xg_acui_grid", "xg_preprocess_rgb",
             "xg_render_fwd_rgb", "xg_render_fwd_l1", "xg_preprocess_bwd_write", "xg_render_bwd_2d",
-            "xg_render_bwd_store_2d", "xg_ws_inspect", "xg_pair_keys")
+            "xg_render_bwd_store_2d", "xg_ws_inspect", "xg_pair_keys", "xg_loss_grad_static")
+STATIC_SCRATCH_BYTES = 32 << 20
 MAX_STORE_SLOTS = 4096
 
 
@@ -356,6 +359,12 @@ def xg_loss_grad(frame: XgFrame, image: int, target: int, gamma: float, dl_dimag
                  loss: int = 0, stream: int = 0) -> None:
     _check(_L.xg_loss_grad(C.byref(frame), image, target, gamma, dl_dimage, loss or None, stream),
            "xg_loss_grad")
+
+
+def xg_loss_grad_static(frame: XgFrame, image: int, target: int, gamma: float, dl_dimage: int,
+                        loss: int = 0, stream: int = 0) -> None:
+    _check(_L.xg_loss_grad_static(C.byref(frame), image, target, gamma, dl_dimage, loss or None,
+                                  stream), "xg_loss_grad_static")
 
 
 def xg_adam_step(params: XgParams, grads: XgGrads, m: int, v: int, step: int, cfg: XgAdam,

@@ -608,6 +608,27 @@ xg_status xg_loss_grad(const xg_frame *f, const float *image, const float *targe
                                        gamma, dl_dimage, loss, (hipStream_t)stream));
 }
 
+xg_status xg_loss_grad_static(const xg_frame *f, const float *image, const float *target, float gamma,
+                              float *dl_dimage, float *loss, void *stream) {
+    Plan P;
+    xg_status st = make_plan(f, false, P);
+    if (st != XG_OK) return st;
+    if (!f->cams_dev || !image || !target || !dl_dimage) return XG_EINVAL;
+    if (!(gamma >= 0.0f && gamma <= 1.0f)) return XG_EINVAL;
+    const int64_t strips = loss_tiles(f->cams, f->n_views);
+    if (12 * P.total_px + 4 * strips > (int64_t)XG_STATIC_SCRATCH_BYTES) return XG_ECAPACITY;
+    float *scratch = nullptr;
+    const hipError_t e = static_scratch(&scratch);
+    if (e != hipSuccess) return hip_status(e);
+    Ws ws;
+    memset(&ws, 0, sizeof(ws));
+    ws.ssim = scratch;
+    ws.total_pixels = P.total_px;
+    ws.n_views = f->n_views;
+    return hip_status(launch_loss_grad(ws, f->cams_dev, strips, image, target, gamma, dl_dimage, loss,
+                                       (hipStream_t)stream));
+}
+
 xg_status xg_rirf_fwd(const float *features, const float *weights, int32_t n, int32_t n_features,
                       float *intensity, void *stream) {
     if (n < 0 || n_features < 1 || n_features > XG_MAX_FEATURES) return XG_EINVAL;

@@ -199,6 +199,9 @@ hipError_t launch_render_fwd_rgb(const Ws &ws, const xg_camera *cams, const Para
 hipError_t launch_acui_grid(const double size[3], const int32_t grid[3], double d, const int32_t k[3],
                             int64_t count, float *means, hipStream_t s);
 int64_t loss_tiles(const xg_camera *cams_host, int n_views);
+// this device's address of the static scratch array of xg_loss_grad_static
+// (resolved on the first call on each device)
+hipError_t static_scratch(float **out);
 hipError_t launch_loss_grad(const Ws &ws, const xg_camera *cams_dev, int64_t tiles,
                             const float *image, const float *target, float gamma, float *dl,
                             float *loss, hipStream_t s);

@@ -29,6 +29,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace xg {
 
 namespace {
@@ -275,7 +277,38 @@ __global__ __launch_bounds__(kSumThreads) void k_loss_sum(const float *partial, 
     }
 }
 
+// Per-device addresses of the scratch array below, resolved on the first
+// call on each device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices];
+
 }  // namespace
+
+// Scratch of the allocation-free loss gradient (xg_loss_grad_static): the
+// three per-pixel maps and the per-strip loss shares of one call.  Each
+// device that loads the library holds its own copy until the process ends.
+// Host code never passes this name to a kernel (on the host it is only a
+// stand-in for the symbol): it resolves each device's address once, with
+// hipGetSymbolAddress, and passes that address.
+__device__ __align__(256) float scratch[XG_STATIC_SCRATCH_BYTES / sizeof(float)];
+
+hipError_t static_scratch(float **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 int64_t loss_tiles(const xg_camera *cams, int n_views) {
     int64_t t = 0;

@@ -181,6 +181,23 @@ def test_invalid_frames_rejected_before_any_hip_call():
         with pytest.raises(X.XgError) as e:
             X.xg_loss_grad(f4, 4096, 4096, gamma, 8192)
         assert e.value.status == X.XG_EINVAL
+    # the allocation-free form: no workspace needed, but device cameras and
+    # images are; maps beyond the static array are refused before any HIP call
+    f5, _ = _frame()
+    with pytest.raises(X.XgError) as e:
+        X.xg_loss_grad_static(f5, 4096, 4096, 0.2, 8192)
+    assert e.value.status == X.XG_EINVAL
+    f5.cams_dev = 256
+    for args in ((0, 4096, 0.2, 8192), (4096, 4096, 1.5, 8192), (4096, 4096, 0.2, 0)):
+        with pytest.raises(X.XgError) as e:
+            X.xg_loss_grad_static(f5, *args)
+        assert e.value.status == X.XG_EINVAL
+    big, _ = _frame(views=((2048, 2048),))
+    big.cams_dev = 256
+    with pytest.raises(X.XgError) as e:
+        X.xg_loss_grad_static(big, 4096, 4096, 0.2, 8192)
+    assert e.value.status == X.XG_ECAPACITY
+    assert 12 * 2048 * 2048 > X.STATIC_SCRATCH_BYTES >= 12 * 8 * 512 * 512 + 4 * 8 * 11 * 64
 
 
 def test_package_fails_loudly_without_library(tmp_path):
