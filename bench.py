@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds", type=int, default=256)
     ap.add_argument("--persistent", type=int, default=0, help="persistent blending kernels (1/0)")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the on-device HBM / VALU / LDS microbenchmarks")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick tile and LDS batch with the autotuner on this scene (timed fwd+bwd "
+                         "steps over the 9 settings, before the benchmark) instead of --tile/--lds")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -266,6 +271,84 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def measured_peaks(dev, stream) -> dict:
+    """On-device ceilings from libxgpeaks.so (HIP events on `stream`):
+    streaming copy and read of 1 GiB (HBM), independent scalar FP32 FMA
+    chains (VALU issue rate in lane-operations/s), conflict-free 16-byte LDS
+    reads (LDS bandwidth).  Best of 5 launches each."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2403_04116_amd", "libxgpeaks.so"))
+    for name, args in (("xgp_copy", [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
+                       ("xgp_read", [C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p]),
+                       ("xgp_valu", [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+                       ("xgp_lds", [C.c_void_p, C.c_int, C.c_int, C.c_void_p])):
+        getattr(lib, name).argtypes = args
+        getattr(lib, name).restype = C.c_int
+    sid = C.c_void_p(int(stream.cuda_stream))
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1 << 16, dtype=torch.float32, device=dev)
+
+    def best_ms(fn, reps=5):
+        assert fn() == 0
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return min(out)
+
+    n16 = nbytes // 16
+    blocks = cus * 16
+    copy_ms = best_ms(lambda: lib.xgp_copy(src.data_ptr(), dst.data_ptr(), n16, blocks, sid))
+    read_ms = best_ms(lambda: lib.xgp_read(src.data_ptr(), n16, sink.data_ptr(), blocks, sid))
+    iters = 8192
+    wg = cus * 8
+    valu_ms = best_ms(lambda: lib.xgp_valu(sink.data_ptr(), iters, wg, sid))
+    lds_ms = best_ms(lambda: lib.xgp_lds(sink.data_ptr(), iters, wg, sid))
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    return {"cus": cus,
+            "hbm_copy_GBps": 2 * nbytes / (copy_ms * 1e-3) / 1e9,
+            "hbm_read_GBps": nbytes / (read_ms * 1e-3) / 1e9,
+            "valu_T_lane_ops": wg * 256 * iters * 8 / (valu_ms * 1e-3) / 1e12,
+            "lds_TBps": wg * 256 * iters * 16 / (lds_ms * 1e-3) / 1e12,
+            "lds_B_per_clk_per_cu_at_2p4GHz": wg * 256 * iters * 16 / (lds_ms * 1e-3) / cus / 2.4e9}
+
+
+# Lists by counting are used when every view has at most this many tiles
+# (the library's limit); otherwise emission and the radix sort of the pairs.
+BIN_MAX_TILES = 4096
+BIN_ITEMS = 2048
+
+
+def bin_sort_bytes(frame, w, n_items, n_kept, npairs, item_passes, pair_passes):
+    """Bytes the binning stage must move: the item sort (key and value read
+    and written per pass, the key histogram, the sorted counts), the count
+    scan, then either the lists by counting (the kept items' slot, count and
+    value read twice, the per-partition tile counts written, scanned and
+    read, each pair written once, the tile ranges) or emission and the pair
+    passes (each pair written, histogrammed, read and written per pass and
+    read for the ranges)."""
+    tile = frame.settings.tile
+    view_tiles = [((wd + tile - 1) // tile) * ((ht + tile - 1) // tile) for wd, ht in w.sizes]
+    pair_word = 4 if frame.layout.pair_index_bits else 8
+    items = n_items * (4 + 24 * item_passes + 4) + 16 * n_kept + 8 * n_items
+    if max(view_tiles) <= BIN_MAX_TILES:
+        rows = w.n_views * ((w.n + BIN_ITEMS - 1) // BIN_ITEMS)
+        return items + 2 * 16 * n_kept + 16 * rows * max(view_tiles) + pair_word * npairs \
+            + 16 * frame.total_tiles
+    return items + npairs * (pair_word + 4 + 2 * pair_word * pair_passes + 4) + 8 * frame.total_tiles
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -305,6 +388,15 @@ def main():
 
     stream = torch.cuda.current_stream()
     del gt_t
+    tuned = None
+    if args.autotune:
+        from paper_2403_04116_amd.autotune import autotune
+        res = autotune(g, cams, target, scale, use_cache=False)
+        best = res["settings"]
+        args.tile, args.lds = int(best.tile), int(best.lds_batch)
+        st = P.settings(tile=args.tile, lds_batch=args.lds, persistent=bool(args.persistent))
+        tuned = {"tile": args.tile, "lds_batch": args.lds,
+                 "ms_per_step": {f"{t}x{b}": round(v, 4) for (t, b), v in sorted(res["ms"].items())}}
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
 
@@ -441,8 +533,7 @@ def main():
     work = {
         "zero_grads": ("hbm", 48 * w.n),
         "preprocess": ("hbm", 48 * w.n + (64 + 4 + 8 + 32) * n_items),
-        "bin_sort": ("hbm", n_items * (4 + 16 * item_passes + 8 + 12) + 16 * n_kept
-                     + npairs * (8 + 4 + 16 * pair_passes + 4) + 8 * frame.total_tiles),
+        "bin_sort": ("hbm", bin_sort_bytes(frame, w, n_items, n_kept, npairs, item_passes, pair_passes)),
         "render_fwd": ("alu", fwd_ops),
         "render_fwd_l1": ("alu", fwd_ops),   # plus 12 bytes per pixel for the L1 epilogue
         "l1_grad": ("hbm", 12 * npx),
@@ -646,7 +737,8 @@ def main():
                    "gaussians": w.n, "views": w.n_views,
                    "detector": "x".join(map(str, w.sizes[0])) if len(set(w.sizes)) == 1 else "mixed",
                    "tile": args.tile, "lds_batch": args.lds, "persistent": bool(args.persistent),
-                   "store_slots": args.store, "adam": opt is not None, "path": "batched"},
+                   "store_slots": args.store, "adam": opt is not None, "path": "batched",
+                   "autotuned": tuned},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
                      "frac": achieved / PEAK_LANE_OPS,
@@ -672,6 +764,7 @@ def main():
         "wall_s": wall_b,
         "kernel_source_hash": kernel_source_hash(),
         "hbm": hbm,
+        "measured_peaks": None if args.no_peaks else measured_peaks(dev, stream),
     }
     print(json.dumps(res))
 

@@ -17,7 +17,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libxg.so")
-SOURCES = ["api.cpp", "preprocess.hip", "scan.hip", "sort.hip", "render.hip", "adam.hip", "loss.hip", "init.hip", "sh.hip"]
+# on-device peak microbenchmarks used by the benchmark (not part of libxg)
+PEAKS_SRC = "peaks.hip"
+PEAKS_LIB = os.path.join(PKG, "libxgpeaks.so")
+SOURCES = ["api.cpp", "preprocess.hip", "scan.hip", "sort.hip", "bin.hip", "render.hip", "adam.hip", "loss.hip", "init.hip", "sh.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -40,16 +43,23 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compiles and links libxg.so; returns its path.  Always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES) + 1, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + [PEAKS_SRC]))
+    peaks_obj = objs.pop()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmp = PEAKS_LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, peaks_obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAKS_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAKS_LIB}")
     return LIB
 
 

@@ -70,9 +70,10 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 
 struct Plan {
     xg_ws_layout lay;
-    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, lookback[2], tile_order, ssim;
+    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, vhist, bin_cnt, lookback[2],
+        tile_order, ssim;
     int64_t total_px, total_tiles, n_items;
-    int32_t item_blocks, pair_blocks, tile_bits, pair_passes, pair_gbits;
+    int32_t item_blocks, pair_blocks, tile_bits, pair_passes, pair_gbits, bin_tiles, bin_ppv;
 };
 
 int bits_of(int64_t v) { return v <= 0 ? 0 : 64 - __builtin_clzll((unsigned long long)v); }
@@ -83,7 +84,16 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     const int64_t ni = (int64_t)f->n * f->n_views;
     const int64_t cap = f->pair_capacity;
     P.n_items = ni;
-    P.item_blocks = (int32_t)((ni + kItemSortBlock - 1) / kItemSortBlock);
+    // the items are sorted within each view: every view starts a partition
+    P.item_blocks = (int32_t)((int64_t)f->n_views * (((int64_t)f->n + kItemSortBlock - 1) / kItemSortBlock));
+    // tile lists by counting when every view has at most kBinMaxTiles tiles
+    int64_t max_view_tiles = 0;
+    for (int v = 0; v < f->n_views; ++v) {
+        const int64_t t = tiles_of(f->cams[v], f->settings.tile);
+        if (t > max_view_tiles) max_view_tiles = t;
+    }
+    P.bin_tiles = max_view_tiles <= kBinMaxTiles ? (int32_t)max_view_tiles : 0;
+    P.bin_ppv = (int32_t)(((int64_t)f->n + kBinItems - 1) / kBinItems);
     P.tile_bits = bits_of(P.total_tiles - 1);
     P.pair_passes = (P.tile_bits + kRadixBits - 1) / kRadixBits;
     // one word per pair when tile id and Gaussian index fit 32 bits together
@@ -115,6 +125,8 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
         if (P.pair_gbits == 0) o = align_up(o + 4 * (size_t)cap);
     }
     P.ghist = o;              o = align_up(o + 4 * (size_t)kSortCtlWords);
+    P.vhist = o;              o = align_up(o + 4 * (size_t)f->n_views * kMaxPasses * kRadix);
+    P.bin_cnt = o;            o = align_up(o + 4 * (size_t)f->n_views * P.bin_ppv * P.bin_tiles);
     for (int b = 0; b < 2; ++b) { P.lookback[b] = o; o = align_up(o + 8 * (size_t)lb_words); }
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
     L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
@@ -144,6 +156,10 @@ Ws resolve(const xg_frame *f, const Plan &P) {
         w.pval[k] = (uint32_t *)(b + P.pval[k]);
     }
     w.ghist = (uint32_t *)(b + P.ghist);
+    w.vhist = (uint32_t *)(b + P.vhist);
+    w.bin_cnt = (uint32_t *)(b + P.bin_cnt);
+    w.bin_tiles = P.bin_tiles;
+    w.bin_ppv = P.bin_ppv;
     w.pctr = w.ghist + kMaxPasses * kRadix * kGhStride;
     w.lookback[0] = (uint64_t *)(b + P.lookback[0]);
     w.lookback[1] = (uint64_t *)(b + P.lookback[1]);
@@ -311,10 +327,17 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
         if (e == hipSuccess)
             e = launch_scan(ws.icounts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
                             &ws.hdr->status, ws.cap, s);
-        if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
-        if (e == hipSuccess) e = launch_sort_pairs(ws, s);
+        if (ws.bin_tiles > 0) {
+            // the lists by counting (writes every tile range)
+            if (e == hipSuccess) e = launch_bin_lists(ws, f->cams_dev, p, s);
+        } else {
+            if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
+            if (e == hipSuccess) e = launch_sort_pairs(ws, s);
+            if (e == hipSuccess) e = launch_ranges(ws, true, s);
+        }
+    } else {
+        e = launch_ranges(ws, false, s);
     }
-    if (e == hipSuccess) e = launch_ranges(ws, ws.n_items > 0, s);
     return hip_status(e);
 }
 

@@ -1,0 +1,307 @@
+// Stage 2 (Sec. 3.2), the per-tile depth-ordered Gaussian lists, built by
+// counting instead of sorting the pairs.
+//
+// The items (view, Gaussian) are sorted by depth within each view, so the
+// items of view v sit in [v n, (v + 1) n) in (depth, Gaussian index)
+// order, and their scanned tile counts give every item its pair slots.  A
+// tile only lists Gaussians of its own view, in item order.  The lists are
+// therefore a stable counting sort of each view's pairs by view-local tile
+// id, whose digit range (the view's tiles, at most kBinMaxTiles) is small
+// enough to count in LDS:
+//   1. k_bin_count: per partition (kBinItems consecutive items of one
+//      view), the number of pairs of each tile (LDS atomics over the items'
+//      tile rectangles) -> one row of bin_cnt;
+//   2. k_bin_columns: down each (view, tile) column of bin_cnt, the
+//      exclusive scan over the view's partitions, and the tile's total;
+//   3. k_bin_starts: per view, the exclusive scan of the tile totals from
+//      the view's first pair slot -> the tile ranges [start, end);
+//   4. k_bin_scatter: per partition, the pairs in windows of kBinWindow
+//      slots: emitted into LDS in slot order, ranked stably within the
+//      window by wavefront ballots on the tile id (per-wavefront counters,
+//      then a prefix over the wavefronts), and written at tile start +
+//      column prefix + rank.
+// The result is the same (tile, depth, index) order as the radix sort of
+// the pairs, element for element; no pair is read back from memory.
+#include "common.h"
+
+namespace xg {
+
+namespace {
+
+struct BinPart {
+    int view, q;
+    int64_t j0, j1;   // items [j0, j1) of the partition
+    int tiles_x, tiles, toff;
+};
+
+__device__ __forceinline__ BinPart bin_part(const Ws &ws, const xg_camera *cams, int tile) {
+    BinPart b;
+    b.view = blockIdx.x / ws.bin_ppv;
+    b.q = blockIdx.x - b.view * ws.bin_ppv;
+    const int64_t vbase = (int64_t)b.view * ws.n;
+    b.j0 = vbase + (int64_t)b.q * kBinItems;
+    b.j1 = min(b.j0 + kBinItems, vbase + ws.n);
+    const xg_camera &c = cams[b.view];
+    b.tiles_x = (c.width + tile - 1) / tile;
+    b.tiles = b.tiles_x * ((c.height + tile - 1) / tile);
+    b.toff = c.tile_offset;
+    return b;
+}
+
+constexpr int kCountThreads = 256;
+
+__global__ __launch_bounds__(kCountThreads) void k_bin_count(Ws ws, const xg_camera *cams, int tile) {
+    __shared__ uint32_t cnt[kBinMaxTiles];
+    const BinPart b = bin_part(ws, cams, tile);
+    for (int t = threadIdx.x; t < b.tiles; t += kCountThreads) cnt[t] = 0;
+    __syncthreads();
+    const int sel = ws.hdr->item_sel & 1;
+    for (int64_t j = b.j0 + threadIdx.x; j < b.j1; j += kCountThreads) {
+        if (ws.icounts[j] == 0) continue;
+        const TileRect r = item_tile_rect(ws, ws.ivals[sel][j], tile);
+        for (int ty = r.ty0; ty <= r.ty1; ++ty)
+            for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&cnt[ty * b.tiles_x + tx], 1u);
+    }
+    __syncthreads();
+    uint32_t *row = ws.bin_cnt + (int64_t)blockIdx.x * ws.bin_tiles;
+    for (int t = threadIdx.x; t < b.tiles; t += kCountThreads) row[t] = cnt[t];
+}
+
+// One thread per (view, local tile): exclusive scan down the column of the
+// view's partitions (rewritten in place); the total goes to the tile's
+// range start word until k_bin_starts replaces it.
+constexpr int kColThreads = 256;
+
+__global__ __launch_bounds__(kColThreads) void k_bin_columns(Ws ws, const xg_camera *cams, int tile,
+                                                             int chunks) {
+    const int v = blockIdx.x / chunks;
+    const int t = (blockIdx.x - v * chunks) * kColThreads + threadIdx.x;
+    const xg_camera &c = cams[v];
+    const int tiles = ((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
+    if (t >= tiles) return;
+    const int64_t stride = ws.bin_tiles;
+    uint32_t *col = ws.bin_cnt + (int64_t)v * ws.bin_ppv * stride + t;
+    uint32_t run = 0;
+    int q = 0;
+    // eight loads in flight per step
+    for (; q + 8 <= ws.bin_ppv; q += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = col[(int64_t)(q + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            col[(int64_t)(q + k) * stride] = run;
+            run += x[k];
+        }
+    }
+    for (; q < ws.bin_ppv; ++q) {
+        const uint32_t x = col[(int64_t)q * stride];
+        col[(int64_t)q * stride] = run;
+        run += x;
+    }
+    ws.ranges[2 * ((int64_t)c.tile_offset + t)] = run;
+}
+
+// One workgroup per view: tile ranges from the tile totals.  The view's
+// pairs start at the scanned slot of its first item.  Empty tiles, and all
+// tiles once the capacity is exceeded, read (0, 0).
+constexpr int kStartThreads = 1024;
+
+__global__ __launch_bounds__(kStartThreads) void k_bin_starts(Ws ws, const xg_camera *cams, int tile) {
+    __shared__ uint32_t lds[kStartThreads / kWave + 1];
+    const int v = blockIdx.x;
+    const xg_camera &c = cams[v];
+    const int tiles = ((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
+    const bool ok = ws.hdr->status == XG_OK;
+    uint32_t carry = ws.offsets[(int64_t)v * ws.n];
+    uint32_t *rg = ws.ranges + 2 * (int64_t)c.tile_offset;
+    for (int t0 = 0; t0 < tiles; t0 += kStartThreads) {
+        const int t = t0 + threadIdx.x;
+        const uint32_t n = t < tiles ? rg[2 * t] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(n, lds, &tot);
+        if (t < tiles) {
+            const bool live = ok && n > 0;
+            rg[2 * t] = live ? carry + ex : 0u;
+            rg[2 * t + 1] = live ? carry + ex + n : 0u;
+        }
+        carry += tot;
+    }
+}
+
+// Stable ranking and placement of one partition's pairs.  NW wavefronts;
+// LT = the most view-local tiles supported (LB bits).  Per window: the
+// pairs of slots [w0, w0 + kBinWindow) are emitted into LDS in slot order;
+// wavefront w ranks its kBinWindow / NW consecutive slots, row by row, with
+// a 16-bit counter per tile (two per word, LDS atomics from one leader lane
+// per tile in a row); a prefix over the wavefronts then turns the counters
+// into each wavefront's offset inside the window, and every pair lands at
+// base[tile] + that offset + its rank, where base[tile] = the tile's start
+// + the column prefix of the partition + the window's predecessors.
+template <int LT, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_bin_scatter(Ws ws, const xg_camera *cams, int tile) {
+    constexpr int NT = NW * kWave;
+    constexpr int LB = LT <= 1024 ? 10 : 12;
+    constexpr int kRows = kBinWindow / NT;         // rows of 64 slots per wavefront
+    constexpr int kMyItems = kBinItems / NT;       // items per thread
+    static_assert(LT <= (1 << LB) && kBinWindow % NT == 0 && kBinItems % NT == 0, "shape");
+    static_assert(kBinWindow <= 65535, "window offsets and counts fit 16 bits");
+    __shared__ uint32_t h16[NW][LT / 2];
+    __shared__ uint32_t base[LT];
+    __shared__ uint16_t s_lt[kBinWindow];
+    __shared__ uint32_t s_gi[kBinWindow];
+
+    if (ws.hdr->status != XG_OK) return;
+    const BinPart b = bin_part(ws, cams, tile);
+    if (b.j0 >= b.j1) return;
+    const uint32_t S = ws.offsets[b.j0];
+    const uint32_t E = ws.offsets[b.j1 - 1] + ws.icounts[b.j1 - 1];
+    if (S == E) return;
+
+    const uint32_t *colp = ws.bin_cnt + (int64_t)blockIdx.x * ws.bin_tiles;
+    for (int t = threadIdx.x; t < b.tiles; t += NT)
+        base[t] = ws.ranges[2 * ((int64_t)b.toff + t)] + colp[t];
+
+    // this thread's items: slot range, view-local tile rectangle, index
+    const int sel = ws.hdr->item_sel & 1;
+    uint32_t i_off[kMyItems], i_cnt[kMyItems], i_gi[kMyItems];
+    TileRect i_r[kMyItems];
+#pragma unroll
+    for (int k = 0; k < kMyItems; ++k) {
+        const int64_t j = b.j0 + (int64_t)k * NT + threadIdx.x;
+        i_cnt[k] = 0;
+        i_off[k] = 0;
+        i_gi[k] = 0;
+        i_r[k] = TileRect{0, 0, 0, 0};
+        if (j < b.j1) {
+            i_cnt[k] = ws.icounts[j];
+            if (i_cnt[k] > 0) {
+                const uint64_t val = ws.ivals[sel][j];
+                i_off[k] = ws.offsets[j];
+                i_gi[k] = (uint32_t)val - (uint32_t)b.view * (uint32_t)ws.n;
+                i_r[k] = item_tile_rect(ws, val, tile);
+            }
+        }
+    }
+
+    const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    const int gb = ws.pair_gbits;
+    uint32_t *out_t = ws.ptile[ws.pair_sel];
+    uint32_t *out_v = ws.pval[ws.pair_sel];
+
+    for (uint32_t w0 = S; w0 < E; w0 += kBinWindow) {
+        const uint32_t w1 = min(E, w0 + (uint32_t)kBinWindow);
+        const int wn = (int)(w1 - w0);
+        for (int k = threadIdx.x; k < NW * (LT / 2); k += NT) (&h16[0][0])[k] = 0u;
+        // emission: each item writes its pairs inside the window, row-major
+        // over its rectangle
+#pragma unroll
+        for (int k = 0; k < kMyItems; ++k) {
+            const uint32_t a = max(i_off[k], w0), e = min(i_off[k] + i_cnt[k], w1);
+            if (i_cnt[k] == 0 || a >= e) continue;
+            const uint32_t rw = (uint32_t)(i_r[k].tx1 - i_r[k].tx0 + 1);
+            const uint32_t m = a - i_off[k];
+            int ty = i_r[k].ty0 + (int)(m / rw);
+            int tx = i_r[k].tx0 + (int)(m % rw);
+            for (uint32_t s = a; s < e; ++s) {
+                s_lt[s - w0] = (uint16_t)(ty * b.tiles_x + tx);
+                s_gi[s - w0] = i_gi[k];
+                if (++tx > i_r[k].tx1) {
+                    tx = i_r[k].tx0;
+                    ++ty;
+                }
+            }
+        }
+        __syncthreads();
+        // ranking: wavefront w owns slots [w kRows 64, (w + 1) kRows 64)
+        uint32_t rank[kRows], tl[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int slot = (w * kRows + r) * kWave + lane;
+            const bool valid = slot < wn;
+            const uint32_t t = valid ? s_lt[slot] : 0u;
+            tl[r] = t;
+            const uint64_t peers = match_peers<LB>(t, valid);
+            const int leader = __ffsll((unsigned long long)peers) - 1;
+            uint32_t old = 0;
+            if (valid && lane == leader) {
+                const uint32_t sh = 16u * (t & 1u);
+                old = (atomicAdd(&h16[w][t >> 1], (uint32_t)__popcll(peers) << sh) >> sh) & 0xffffu;
+            }
+            old = (uint32_t)__shfl((int)old, leader < 0 ? 0 : leader, kWave);
+            rank[r] = old + (uint32_t)__popcll(peers & lt_mask);
+        }
+        __syncthreads();
+        // prefix over the wavefronts, two tiles (one word) per step
+        constexpr int kPairsPerThread = (LT / 2 + NT - 1) / NT;
+        uint32_t adv[kPairsPerThread];
+#pragma unroll
+        for (int k = 0; k < kPairsPerThread; ++k) {
+            const int tw = k * NT + threadIdx.x;
+            uint32_t run = 0;   // two 16-bit sums
+            if (tw < LT / 2) {
+#pragma unroll
+                for (int x = 0; x < NW; ++x) {
+                    const uint32_t hcur = h16[x][tw];
+                    h16[x][tw] = run;
+                    run += hcur;   // neither half exceeds kBinWindow: no carry
+                }
+            }
+            adv[k] = run;
+        }
+        __syncthreads();
+        // placement
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int slot = (w * kRows + r) * kWave + lane;
+            if (slot < wn) {
+                const uint32_t t = tl[r];
+                const uint32_t off = (h16[w][t >> 1] >> (16u * (t & 1u))) & 0xffffu;
+                const uint32_t dst = base[t] + off + rank[r];
+                const uint32_t gt = (uint32_t)b.toff + t;
+                const uint32_t gi = s_gi[slot];
+                if (dst >= (uint64_t)ws.cap) continue;   // never: the counts add up to the slots
+                if (gb) {
+                    out_t[dst] = (gt << gb) | gi;
+                } else {
+                    out_t[dst] = gt;
+                    out_v[dst] = gi;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPairsPerThread; ++k) {
+            const int tw = k * NT + threadIdx.x;
+            if (tw < LT / 2) {
+                if (2 * tw < b.tiles) base[2 * tw] += adv[k] & 0xffffu;
+                if (2 * tw + 1 < b.tiles) base[2 * tw + 1] += adv[k] >> 16;
+            }
+        }
+        // the next window's counters are cleared before its ranking, after
+        // the barrier that follows its emission; base is next read after that
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bin_lists(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s) {
+    if (ws.bin_tiles <= 0 || ws.bin_tiles > kBinMaxTiles || ws.bin_ppv <= 0) return hipErrorInvalidValue;
+    const int64_t parts = (int64_t)ws.n_views * ws.bin_ppv;
+    if (parts > 0x7fffffff) return hipErrorInvalidValue;
+    const unsigned np = (unsigned)parts;
+    hipLaunchKernelGGL(k_bin_count, dim3(np), dim3(kCountThreads), 0, s, ws, cams, p.tile);
+    const int chunks = (ws.bin_tiles + kColThreads - 1) / kColThreads;
+    hipLaunchKernelGGL(k_bin_columns, dim3((unsigned)(ws.n_views * chunks)), dim3(kColThreads), 0, s, ws,
+                       cams, p.tile, chunks);
+    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)ws.n_views), dim3(kStartThreads), 0, s, ws, cams, p.tile);
+    if (ws.bin_tiles <= 1024)
+        hipLaunchKernelGGL((k_bin_scatter<1024, 16>), dim3(np), dim3(16 * kWave), 0, s, ws, cams, p.tile);
+    else
+        hipLaunchKernelGGL((k_bin_scatter<4096, 8>), dim3(np), dim3(8 * kWave), 0, s, ws, cams, p.tile);
+    return hipGetLastError();
+}
+
+}  // namespace xg

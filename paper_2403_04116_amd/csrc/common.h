@@ -71,6 +71,9 @@ struct Ws {
     uint32_t *ptile[2];    // pair sort keys (global tile id)
     uint32_t *pval[2];     // pair sort values (Gaussian index)
     uint32_t *ghist;       // radix sort: digit histograms [kMaxPasses][kRadix], one 128-byte line each
+    uint32_t *vhist;       // item sort (within each view): digit totals [view][kMaxPasses][kRadix]
+    uint32_t *bin_cnt;     // tile lists by counting: [view][partition][local tile] pair counts,
+                           // then their exclusive scan down each column
     uint32_t *pctr;        // radix sort: partition counters [kMaxPasses]
     uint64_t *lookback[2]; // radix sort: per (partition, digit) aggregate / prefix words
     uint32_t *ranges;
@@ -96,6 +99,11 @@ struct Ws {
     int32_t pair_gbits;
     uint32_t pair_gmask;
     const uint32_t *pair_vals;
+    // Tile lists by counting (bin_tiles > 0): the row length of bin_cnt (the
+    // most tiles of any view) and the partitions of kBinItems items per view.
+    // bin_tiles = 0: emission and the radix sort of the pairs by tile.
+    int32_t bin_tiles;
+    int32_t bin_ppv;
 };
 
 // Scalar constants of one rendering.
@@ -134,6 +142,41 @@ __device__ __forceinline__ bool unpack_tile_rect(uint32_t r, TileRect &t) {
     return true;
 }
 
+// Tile rectangle (first/last tile column and row, view-local) of a sorted
+// item from its sort value: the packed rectangle, else the record.
+__device__ __forceinline__ TileRect item_tile_rect(const Ws &ws, uint64_t val, int tile) {
+    TileRect tr;
+    if (!unpack_tile_rect((uint32_t)(val >> 32), tr)) {
+        const int4 rc = ws.rec[(uint32_t)val].c;
+        tr.tx0 = (rc.z & 0xffff) / tile;
+        tr.tx1 = (rc.z >> 16) / tile;
+        tr.ty0 = (rc.w & 0xffff) / tile;
+        tr.ty1 = (rc.w >> 16) / tile;
+    }
+    return tr;
+}
+
+// Lanes of the wavefront whose BITS-bit key equals this lane's (one ballot
+// per key bit), restricted to `valid` lanes.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_peers(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Tile lists by counting: items per partition (all of one view), pairs per
+// LDS window of the ranking kernel, and the most tiles a view may have on
+// this path (larger views use emission and the radix sort of the pairs).
+constexpr int kBinItems = 2048;
+constexpr int kBinWindow = 4096;
+constexpr int kBinMaxTiles = 4096;
+
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;   // 2048 elements
@@ -163,6 +206,7 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s);
 hipError_t launch_ranges(const Ws &ws, bool cleared, hipStream_t s);  // cleared: by the pair sort
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
+hipError_t launch_bin_lists(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s);
 hipError_t launch_pair_keys(const Ws &ws, const xg_camera *cams, uint64_t *keys, uint32_t *vals,
                             int64_t cap, hipStream_t s);
 // Per-pixel stored transmittances of the stored-list variant: count[tile][px]

@@ -363,15 +363,7 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
         const xg_camera &c = cams[v];
         txn = (c.width + tile - 1) / tile;
         toff = c.tile_offset;
-        TileRect tr;
-        if (!unpack_tile_rect((uint32_t)(val >> 32), tr)) {
-            // rectangle too large to pack: read it from the record
-            const int4 rc = ws.rec[idx].c;
-            tr.tx0 = (rc.z & 0xffff) / tile;
-            tr.tx1 = (rc.z >> 16) / tile;
-            tr.ty0 = (rc.w & 0xffff) / tile;
-            tr.ty1 = (rc.w >> 16) / tile;
-        }
+        const TileRect tr = item_tile_rect(ws, val, tile);
         tx0 = tr.tx0;
         tx1 = tr.tx1;
         ty0 = tr.ty0;

@@ -252,7 +252,6 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
     static_assert(CH == 1 || (CH == 3 && !COUNT && !STORE), "RGB forward: plain variant only");
     static_assert(B % 8 == 0, "list groups of 8 are read 16 bytes at a time");
     constexpr int NT = T * T;
-    constexpr int NW = NT / kWave;
     constexpr int SB = T / 8;
     float4 *s_a = sh.a;
     float4 *s_b = sh.b;

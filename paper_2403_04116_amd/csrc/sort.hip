@@ -1,12 +1,15 @@
 // Stage 2 (Sec. 3.2): the per-tile, depth-ordered Gaussian lists.
 //
 // Two stable LSD radix sorts replace one sort of (tile | depth) keys:
-//   1. items: the (view, Gaussian) records sorted by depth bits alone,
-//      compacted on the fly to (depth bits - depth_min) over only the bits
-//      that vary among kept Gaussians (culled items carry the largest key);
-//      equal keys keep (view, Gaussian) index order;
+//   1. items: the (view, Gaussian) records of each view sorted by depth
+//      bits alone (a segmented sort: view v's items stay in [v n, (v+1) n),
+//      every view starts its own partitions, digit totals and look-back
+//      chains), compacted on the fly to (depth bits - depth_min) over only
+//      the bits that vary among kept Gaussians (culled items carry the
+//      largest key); equal keys keep Gaussian index order;
 //   2. pairs: the (tile, Gaussian) pairs, emitted in that item order, sorted
-//      by tile id only.
+//      by tile id only.  When every view has few enough tiles the lists are
+//      built by counting instead (bin.hip) and this sort is not used.
 // A tile only lists Gaussians of its own view, and those appear in the
 // item order by (depth, Gaussian index); stability carries that order into
 // every tile's list, exactly the order of a sort on (tile << 32 | depth
@@ -69,6 +72,9 @@ struct ItemSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
     static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
     static constexpr bool kHasVal = true;
+    // sorted within each view: the items of view v stay in [v n, (v + 1) n)
+    static constexpr bool kSegmented = true;
+    static __device__ __forceinline__ int64_t seg_len(const Ws &ws) { return ws.n; }
     // passes whose digit is the same for every key could be skipped, but
     // after the compaction to the varying depth bits that is rare, and
     // finding out costs every partition of every pass four block-wide
@@ -108,6 +114,8 @@ struct PairSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPairSortThreads, kItems = kPairSortItems;
     static constexpr bool kHasVal = true;
+    static constexpr bool kSegmented = false;
+    static __device__ __forceinline__ int64_t seg_len(const Ws &) { return 0; }
     static constexpr bool kGatherCounts = false;
     // the tile ranges are cleared here, ahead of k_ranges
     static constexpr bool kClearRanges = true;
@@ -135,6 +143,8 @@ struct PackedPairSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPackedSortThreads, kItems = kPackedSortItems;
     static constexpr bool kHasVal = false;
+    static constexpr bool kSegmented = false;
+    static __device__ __forceinline__ int64_t seg_len(const Ws &) { return 0; }
     static constexpr bool kGatherCounts = false;
     static constexpr bool kClearRanges = true;
     static constexpr bool kSkipConstant = false;
@@ -150,32 +160,56 @@ constexpr uint64_t kLbPrefix = 2ull << 62;      // inclusive prefix through this
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kLookback = 4;     // predecessors read per look-back step
 
+// Partitions of one sort.  Unsegmented: kBlock consecutive keys each.
+// Segmented (the items, sorted within each view): every segment of seg_len
+// keys starts a new partition, so partition p belongs to segment p / ppv.
+template <class S>
+struct Parts {
+    int64_t ppv;     // partitions per segment (all of them when unsegmented)
+    int64_t parts;   // partitions of the sort
+    int64_t seg;     // keys per segment (n when unsegmented)
+    __device__ __forceinline__ Parts(const Ws &ws, const Ctl &c) {
+        constexpr int64_t kBlock = S::kThreads * S::kItems;
+        if constexpr (S::kSegmented) {
+            seg = S::seg_len(ws);
+            ppv = (seg + kBlock - 1) / kBlock;
+            parts = c.n > 0 ? ppv * (c.n / (seg > 0 ? seg : 1)) : 0;
+        } else {
+            seg = c.n;
+            ppv = (c.n + kBlock - 1) / kBlock;
+            parts = ppv;
+        }
+    }
+    // first key of partition p's segment, and the end of that segment
+    __device__ __forceinline__ int64_t seg_base(int64_t p) const { return S::kSegmented ? (p / ppv) * seg : 0; }
+    __device__ __forceinline__ int64_t first_part(int64_t p) const { return S::kSegmented ? (p / ppv) * ppv : 0; }
+};
+
+// Digit totals of a sort: one 128-byte line per (pass, digit) bin for the
+// unsegmented sorts (their histogram atomics come from many workgroups),
+// dense [segment][pass][digit] words for the segmented one.
+template <class S>
+__device__ __forceinline__ uint32_t *digit_bin(const Ws &ws, int64_t segment, int pass, int d) {
+    if constexpr (S::kSegmented)
+        return ws.vhist + (segment * kMaxPasses + pass) * kRadix + d;
+    else
+        return ws.ghist + (pass * kRadix + d) * kGhStride;
+}
+
 // Zeroes the digit histograms, partition counters and the first pass's
 // look-back words of one sort.
 template <class S>
 __global__ __launch_bounds__(256) void k_sort_prep(Ws ws) {
     const Ctl c = S::ctl(ws);
-    constexpr int64_t kBlock = S::kThreads * S::kItems;
-    const int64_t parts = (c.n + kBlock - 1) / kBlock;
+    const int64_t parts = Parts<S>(ws, c).parts;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = i0; i < kSortCtlWords; i += stride) ws.ghist[i] = 0;
+    if (S::kSegmented)
+        for (int64_t i = i0; i < (int64_t)ws.n_views * kMaxPasses * kRadix; i += stride) ws.vhist[i] = 0;
     for (int64_t i = i0; i < parts * kRadix; i += stride) ws.lookback[0][i] = 0;
     if (S::kClearRanges)
         for (int64_t i = i0; i < 2 * ws.total_tiles; i += stride) ws.ranges[i] = 0;
-}
-
-// Lanes of the wavefront whose digit equals this lane's (one ballot per
-// digit bit), restricted to `valid` lanes.
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    return peers;
 }
 
 // Digit histograms of every pass in one read of the keys: LDS counters
@@ -199,23 +233,36 @@ __global__ __launch_bounds__(S::kThreads) void k_sort_hist(Ws ws, int passes) {
         (&hist[0][0][0])[i] = 0;
     __syncthreads();
     const Key *in = S::keys(ws, 0);
-    for (int64_t base = (int64_t)blockIdx.x * kSortBlock; base < c.n;
-         base += (int64_t)gridDim.x * kSortBlock) {
+    // unsegmented: the grid strides over all keys; segmented: workgroup p
+    // counts the keys of partition p into its segment's bins
+    const Parts<S> P(ws, c);
+    int64_t first = (int64_t)blockIdx.x * kSortBlock, end = c.n, stride = (int64_t)gridDim.x * kSortBlock;
+    int64_t segment = 0;
+    if constexpr (S::kSegmented) {
+        const int64_t p = blockIdx.x;
+        segment = P.ppv > 0 ? p / P.ppv : 0;
+        first = P.seg_base(p) + (p - P.first_part(p)) * kSortBlock;
+        end = min(P.seg_base(p) + P.seg, c.n);
+        stride = c.n;   // one partition
+        if (p >= P.parts) end = 0;
+    }
+    for (int64_t base = first; base < end; base += stride) {
         // all loads first (indices clamped into range), then the counting
         Key key[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const int64_t j = base + (int64_t)k * kSortThreads + threadIdx.x;
-            key[k] = in[j < c.n ? j : c.n - 1];
+            key[k] = in[j < end ? j : end - 1];
         }
         for (int q = 0; q < passes; ++q) {
             if (q * kRadixBits >= c.total_bits) break;
 #pragma unroll
             for (int k = 0; k < kSortItems; ++k) {
                 const int64_t j = base + (int64_t)k * kSortThreads + threadIdx.x;
-                if (j < c.n) atomicAdd(&hist[q][S::digit(key[k], c, q * kRadixBits)][copy], 1u);
+                if (j < end) atomicAdd(&hist[q][S::digit(key[k], c, q * kRadixBits)][copy], 1u);
             }
         }
+        if (S::kSegmented) break;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < passes * kRadix; i += kSortThreads) {
@@ -223,7 +270,7 @@ __global__ __launch_bounds__(S::kThreads) void k_sort_hist(Ws ws, int passes) {
         uint32_t h = 0;
 #pragma unroll
         for (int k = 0; k < kHistCopies; ++k) h += hist[q][d][k];
-        if (h) atomicAdd(&ws.ghist[(q * kRadix + d) * kGhStride], h);
+        if (h) atomicAdd(digit_bin<S>(ws, segment, q, d), h);
     }
 }
 
@@ -235,7 +282,8 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     constexpr int kSortBlock = kSortThreads * kSortItems;
     const Ctl c = S::ctl(ws);
     const int shift = pass * kRadixBits;
-    const int64_t parts = (c.n + kSortBlock - 1) / kSortBlock;
+    const Parts<S> PP(ws, c);
+    const int64_t parts = PP.parts;
 
     __shared__ Key skeys[kSortBlock];
     using Val = typename S::Val;
@@ -285,7 +333,13 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     __syncthreads();
     const int64_t part = s_part;
     if (part >= parts) return;
-    const int64_t base = part * kSortBlock;
+    // this partition's keys [base, base + kSortBlock) inside its segment
+    // [sbase, send); its look-back stops at the segment's first partition p0
+    const int64_t sbase = PP.seg_base(part);
+    const int64_t p0 = PP.first_part(part);
+    const int64_t send = S::kSegmented ? min(sbase + PP.seg, c.n) : c.n;
+    const int64_t base = sbase + (part - p0) * kSortBlock;
+    const int64_t segment = S::kSegmented ? part / PP.ppv : 0;
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -300,16 +354,16 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t j = wbase + (int64_t)r * kWave + lane;
-        const int64_t jc = j < c.n ? j : c.n - 1;
+        const int64_t jc = j < send ? j : send - 1;
         key[r] = kin[jc];
         if constexpr (S::kHasVal) val[r] = vin[jc];
     }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t j = wbase + (int64_t)r * kWave + lane;
-        const bool valid = j < c.n;
+        const bool valid = j < send;
         const uint32_t d = S::digit(key[r], c, shift);
-        const uint64_t peers = digit_peers(d, valid);
+        const uint64_t peers = match_peers<kRadixBits>(d, valid);
         uint32_t old = 0;
         const int leader = __ffsll((unsigned long long)peers) - 1;
         if (valid && lane == leader) old = atomicAdd(&whist[w][d], (uint32_t)__popcll(peers));
@@ -332,21 +386,20 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
             whist[k][d] = acc;
             acc += t;
         }
-        __hip_atomic_store(lb + part * kRadix + d, (part == 0 ? kLbPrefix : kLbAggregate) | acc,
+        __hip_atomic_store(lb + part * kRadix + d, (part == p0 ? kLbPrefix : kLbAggregate) | acc,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // global start of digit d (keys with smaller digits) and its start in
     // this partition
     uint32_t tot;
-    const uint32_t dstart = block_excl_scan(dig ? ws.ghist[(pass * kRadix + d) * kGhStride] : 0u,
-                                            scan_lds, &tot);
+    const uint32_t dstart = block_excl_scan(dig ? *digit_bin<S>(ws, segment, pass, d) : 0u, scan_lds, &tot);
     const uint32_t bs = block_excl_scan(acc, scan_lds, &tot);
     if (dig) bstart[d] = bs;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t j = wbase + (int64_t)r * kWave + lane;
-        if (j < c.n) {
+        if (j < send) {
             const uint32_t dr = S::digit(key[r], c, shift);
             const uint32_t pos = bstart[dr] + whist[w][dr] + rank[r];
             skeys[pos] = key[r];
@@ -359,13 +412,13 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
         // predecessor that has not published yet is polled again.
         uint32_t excl = 0, spins = 0;
         bool failed = false;
-        for (int64_t q = part - 1; q >= 0;) {
+        for (int64_t q = part - 1; q >= p0;) {
             uint64_t word[kLookback];
 #pragma unroll
             for (int k = 0; k < kLookback; ++k)
-                word[k] = (q - k >= 0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : kLbPrefix;     // before partition 0: prefix 0
+                word[k] = (q - k >= p0) ? __hip_atomic_load(lb + (q - k) * kRadix + d, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                        : kLbPrefix;     // before the segment's first partition: prefix 0
             int used = 0;
             bool stop = false, wait = false;
 #pragma unroll
@@ -390,15 +443,15 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        if (part != 0)
+        if (part != p0)
             __hip_atomic_store(lb + part * kRadix + d, kLbPrefix | (uint32_t)(excl + acc), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         if (failed) __hip_atomic_store(&ws.hdr->status, (int32_t)XG_EHIP, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-        goff[d] = dstart + excl;
+        goff[d] = (uint32_t)sbase + dstart + excl;
     }
     __syncthreads();
-    const int64_t nvalid = min((int64_t)kSortBlock, c.n - base);
+    const int64_t nvalid = min((int64_t)kSortBlock, send - base);
     Key *kout = S::keys(ws, in_sel ^ 1);
     Val *vout = S::vals(ws, in_sel ^ 1);
 #pragma unroll 4
@@ -408,7 +461,7 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
             const Key kk = skeys[pos];
             const uint32_t dk = S::digit(kk, c, shift);
             const uint32_t dst = goff[dk] + (uint32_t)pos - bstart[dk];
-            if (dst < (uint64_t)c.n) {   // always true unless a look-back gave up
+            if (dst < (uint64_t)send) {   // always true unless a look-back gave up
                 kout[dst] = kk;
                 if constexpr (S::kHasVal) {
                     vout[dst] = svals[pos];
@@ -521,7 +574,8 @@ hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s) {
     unsigned np = (unsigned)(((int64_t)blocks * kRadix + 255) / 256);
     if (np > 2048) np = 2048;
     hipLaunchKernelGGL(k_sort_prep<S>, dim3(np > 0 ? np : 1), dim3(256), 0, s, ws);
-    const unsigned nh = nb < 256 ? nb : 256;
+    // segmented sorts: one histogram workgroup per partition
+    const unsigned nh = S::kSegmented ? nb : (nb < 256 ? nb : 256);
     hipLaunchKernelGGL(k_sort_hist<S>, dim3(nh), dim3(S::kThreads), 0, s, ws, passes);
     for (int p = 0; p < passes; ++p)
         hipLaunchKernelGGL(k_onesweep<S>, dim3(nb), dim3(S::kThreads), 0, s, ws, p, passes);

@@ -1,0 +1,87 @@
+"""The per-tile lists (Sec. 3.2) on both of their GPU paths, bit-exact against
+the oracle's sorted (tile << 32 | depth, index) pairs and tile ranges:
+
+- counting (every view has at most 4096 tiles): 8 x 8 tiles on 512 x 512
+  views (4096 tiles, the widest counter rows), partitions whose pairs span
+  many LDS windows (large footprints, some wider than 32 tiles so their
+  rectangle is read from the record), views of uneven size;
+- emission + radix sort of the pairs by tile (a view with more tiles).
+
+Sampled pixels of each run are also checked against the brute-force
+renderer."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenes as S
+from _gpu import compare_pixels, gpu_run, note, oracle_cams
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(g, angles, sizes, tile, label, sample=16):
+    note(f"binning {label}: GPU")
+    gpu = gpu_run(g, angles, sizes, tile=tile, backward=False)
+    assert gpu["status"] == 0
+    st = O.Settings(tile=tile)
+    cams = oracle_cams(angles, sizes)
+    note(f"binning {label}: oracle pairs")
+    pr = O.pairs(g, cams, st)
+    assert pr["keys"].size > 0
+    np.testing.assert_array_equal(gpu["keys"], pr["keys"])
+    np.testing.assert_array_equal(gpu["values"], pr["values"])
+    np.testing.assert_array_equal(gpu["ranges"], pr["ranges"])
+    rng = np.random.default_rng(17)
+    off = 0
+    for v, c in enumerate(cams):
+        npx = c.width * c.height
+        pix = rng.choice(npx, min(sample, npx), replace=False).astype(np.int32)
+        compare_pixels(gpu["image"][off + pix], gpu["final_t"][off + pix], g, c, st, pix,
+                       label=f"{label} view {v}")
+        off += npx
+    return gpu, pr
+
+
+def test_counting_lists_widest_rows():
+    # 8 x 8 tiles on 512 x 512: 4096 tiles per view
+    g = S.gaussians(30000, math.log(0.02), 0.3, 501)
+    gpu, pr = _check(g, [0.2, 2.4], [(512, 512), (512, 512)], 8, "tile 8, 4096 tiles/view")
+    assert int(gpu["frame"].total_tiles) == 8192
+
+
+def test_counting_lists_many_windows_and_wide_rectangles():
+    # large footprints: partitions of 2048 items emit far more than one
+    # window of pairs, and some rectangles are wider than 32 tiles
+    g = S.gaussians(6000, math.log(0.08), 0.5, 502)
+    g["scales"][:40] *= 8.0
+    sizes = [(400, 320), (200, 136), (96, 64)]
+    gpu, pr = _check(g, [0.7, 1.1, 3.0], sizes, 8, "large footprints")
+    assert pr["keys"].size > 3 * 4096
+    # widest rectangle of view 0 in tiles: more than the 32 a packed
+    # rectangle holds, so the record supplies it
+    tiles_x = (sizes[0][0] + 7) // 8
+    t = (pr["keys"] >> 32).astype(np.int64)
+    v0 = t < tiles_x * ((sizes[0][1] + 7) // 8)
+    tx = t[v0] % tiles_x
+    vals = pr["values"][v0].astype(np.int64)
+    lo = np.full(vals.max() + 1, 1 << 30)
+    hi = np.full(vals.max() + 1, -1)
+    np.minimum.at(lo, vals, tx)
+    np.maximum.at(hi, vals, tx)
+    assert (hi - lo + 1).max() > 32
+
+
+def test_counting_lists_uneven_views_tile16():
+    g = S.gaussians(20000, math.log(0.02), 0.3, 503)
+    _check(g, [0.1, 1.3, 2.9, 4.4], [(512, 512), (128, 128), (256, 256), (37, 300)], 16,
+           "uneven views")
+
+
+def test_radix_pair_sort_for_large_views():
+    # 1100 x 1100 with 8 x 8 tiles = 138^2 = 19 044 tiles: above the counting
+    # limit, so the pairs are emitted and radix sorted by tile
+    g = S.gaussians(8000, math.log(0.01), 0.3, 504)
+    gpu, _ = _check(g, [0.4, 2.0], [(1100, 1100), (64, 64)], 8, "large view, radix path")
+    assert int(gpu["frame"].total_tiles) == 138 * 138 + 64
