@@ -49,6 +49,7 @@ __device__ __forceinline__ BinPart bin_part(const Ws &ws, const xg_camera *cams,
 }
 
 constexpr int kCountThreads = 256;
+static_assert(kBinItems % kCountThreads == 0, "whole items per thread");
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(Ws ws, const xg_camera *cams, int tile) {
     __shared__ uint32_t cnt[kBinMaxTiles];
@@ -56,9 +57,20 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(Ws ws, const xg_cam
     for (int t = threadIdx.x; t < b.tiles; t += kCountThreads) cnt[t] = 0;
     __syncthreads();
     const int sel = ws.hdr->item_sel & 1;
-    for (int64_t j = b.j0 + threadIdx.x; j < b.j1; j += kCountThreads) {
-        if (ws.icounts[j] == 0) continue;
-        const TileRect r = item_tile_rect(ws, ws.ivals[sel][j], tile);
+    // every item's count and sort value loaded before any is used
+    constexpr int kPer = kBinItems / kCountThreads;
+    uint32_t n_t[kPer];
+    uint64_t val[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t j = b.j0 + (int64_t)k * kCountThreads + threadIdx.x;
+        n_t[k] = j < b.j1 ? ws.icounts[j] : 0u;
+        val[k] = j < b.j1 ? ws.ivals[sel][j] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (n_t[k] == 0) continue;
+        const TileRect r = item_tile_rect(ws, val[k], tile);
         for (int ty = r.ty0; ty <= r.ty1; ++ty)
             for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&cnt[ty * b.tiles_x + tx], 1u);
     }

@@ -77,6 +77,8 @@ struct Ws {
     uint32_t *pctr;        // radix sort: partition counters [kMaxPasses]
     uint64_t *lookback[2]; // radix sort: per (partition, digit) aggregate / prefix words
     uint32_t *ranges;
+    void *entry_mask;      // per list entry: the 8 x 8 sub-blocks the blending kernels visit
+                           // (written by the forward, read by the backward; 1 byte, 2 for 32 x 32 tiles)
     float *grad2d;
     float *ssim;           // loss: three per-pixel SSIM partial-derivative maps, then one
                            // loss share per 48 x 8 loss strip
@@ -158,16 +160,21 @@ __device__ __forceinline__ TileRect item_tile_rect(const Ws &ws, uint64_t val, i
 
 // Lanes of the wavefront whose BITS-bit key equals this lane's (one ballot
 // per key bit), restricted to `valid` lanes.
+// Per bit: one ballot (a wavefront-uniform mask) and, per half of the
+// mask, one XOR with the lane's all-ones-if-clear word and one AND.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_peers(uint32_t d, bool valid) {
-    uint64_t peers = __ballot(valid);
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const bool bit = (d >> b) & 1u;
+        const uint32_t bit = (d >> b) & 1u;
         const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+        const uint32_t inv = bit - 1u;   // 0 when the bit is set, all ones when clear
+        lo &= (uint32_t)bal ^ inv;
+        hi &= (uint32_t)(bal >> 32) ^ inv;
     }
-    return peers;
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // Tile lists by counting: items per partition (all of one view), pairs per
