@@ -201,7 +201,9 @@ xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
  * pixel of the concatenated images: image (sum of intensity*alpha*T,
  * background 0), final_t (transmittance after the last contributor) and
  * n_contrib (1-based position in the tile list of the last contributor,
- * 0 if none). */
+ * 0 if none).  Also leaves in the workspace, for every list entry it
+ * stages, which 8 x 8 pixel blocks the entry can reach alpha_min in; the
+ * backward reads them (as do the _l1 and _store forms). */
 xg_status xg_render_fwd(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                         float *image, float *final_t, int32_t *n_contrib, void *stream);
 
@@ -234,7 +236,11 @@ xg_status xg_render_bwd(const xg_frame *f /* [host] */, const xg_gaussians *g /*
  * accumulates per (view, Gaussian) the 2-D gradients (image-space centre,
  * inverse 2-D covariance moments, opacity, intensity) in the workspace,
  * reduced across each wavefront before one atomic add per (Gaussian,
- * wavefront).  Follow with xg_preprocess_bwd or xg_preprocess_bwd_write. */
+ * wavefront).  Reads the per-entry block masks the forward left in the
+ * workspace: final_t and n_contrib must come from xg_render_fwd,
+ * xg_render_fwd_l1 or xg_render_fwd_store on these lists (after the last
+ * xg_bin_sort); the comparison model's forward does not write them.
+ * Follow with xg_preprocess_bwd or xg_preprocess_bwd_write. */
 xg_status xg_render_bwd_2d(const xg_frame *f /* [host] */, const float *dl_dimage,
                            const float *final_t, const int32_t *n_contrib, void *stream);
 

@@ -71,7 +71,7 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 struct Plan {
     xg_ws_layout lay;
     size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, vhist, bin_cnt, lookback[2],
-        tile_order, ssim;
+        tile_order, ssim, entry_mask;
     int64_t total_px, total_tiles, n_items;
     int32_t item_blocks, pair_blocks, tile_bits, pair_passes, pair_gbits, bin_tiles, bin_ppv;
 };
@@ -129,6 +129,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.bin_cnt = o;            o = align_up(o + 4 * (size_t)f->n_views * P.bin_ppv * P.bin_tiles);
     for (int b = 0; b < 2; ++b) { P.lookback[b] = o; o = align_up(o + 8 * (size_t)lb_words); }
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
+    P.entry_mask = o;         o = align_up(o + (f->settings.tile > 16 ? 2 : 1) * (size_t)cap);
     L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
     P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
     P.ssim = o;               o = align_up(o + 12 * (size_t)P.total_px + 4 * (size_t)loss_tiles(f->cams, f->n_views));
@@ -164,6 +165,7 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.lookback[0] = (uint64_t *)(b + P.lookback[0]);
     w.lookback[1] = (uint64_t *)(b + P.lookback[1]);
     w.ranges = (uint32_t *)(b + P.lay.ranges);
+    w.entry_mask = b + P.entry_mask;
     w.grad2d = (float *)(b + P.lay.grad2d);
     w.tile_order = (int32_t *)(b + P.tile_order);
     w.ssim = (float *)(b + P.ssim);

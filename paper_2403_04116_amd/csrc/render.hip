@@ -20,6 +20,8 @@
 // bit for bit and can divide the transmittance back.
 #include "common.h"
 
+#include <type_traits>
+
 namespace xg {
 
 namespace {
@@ -151,12 +153,23 @@ __device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, 
 // per-pixel alpha test would skip, so results do not change.
 // DUAL (the counting forward): s_mask keeps the rectangle-only mask and
 // s_cmask receives the culled one.
-template <int T, int NT, bool CULL, bool DUAL = false>
+// MASKIO: 1 (the blending forward) also writes the culled mask of list
+// entry p to the workspace's per-entry mask array; 2 (the backward) reads it
+// from there instead of testing the sub-blocks again.  Every entry the
+// backward stages was staged by the forward of the same lists (a pixel's
+// last contributor lies in a batch the forward staged), and both would
+// compute the same mask.
+template <int T>
+using SubMask = std::conditional_t<(T > 16), uint16_t, uint8_t>;
+
+template <int T, int NT, bool CULL, bool DUAL = false, int MASKIO = 0>
 __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32_t b0, int cnt,
                                       const TileGeom &tg, float amin, float4 *s_a, float4 *s_b,
                                       uint16_t *s_mask, uint32_t *s_rid, float4 *s_c = nullptr,
                                       uint16_t *s_cmask = nullptr) {
     constexpr int SB = T / 8;
+    static_assert(!(MASKIO && DUAL), "the counting forward neither stores nor loads masks");
+    SubMask<T> *gmask = reinterpret_cast<SubMask<T> *>(ws.entry_mask);
     for (int k = threadIdx.x; k < cnt; k += NT) {
         const uint32_t gi = vals[b0 + k] & ws.pair_gmask;   // Gaussian index (packed or not)
         const int64_t rid = (int64_t)tg.view * ws.n + gi;
@@ -173,7 +186,9 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         s_b[k] = make_float4(rb.x, rb.y, rb.z, __uint_as_float(rect));
         uint32_t m = subblock_mask<SB>(xl, xh, yl, yh);
         uint32_t mc = m;
-        if (CULL || DUAL) {
+        if (MASKIO == 2) {
+            m = gmask[b0 + k];
+        } else if (CULL || DUAL) {
             const float thr = __builtin_amdgcn_logf(rb.y * __builtin_amdgcn_rcpf(amin)) * 1.00001f + 1e-3f;
             // pixel centres relative to the Gaussian centre
             const float ox = (float)(tg.x0 - tg.rx) + 0.5f - ux;
@@ -188,6 +203,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
             }
             if (CULL) m = mc;
             if (DUAL) s_cmask[k] = (uint16_t)mc;
+            if (MASKIO == 1) gmask[b0 + k] = (SubMask<T>)m;
         }
         s_mask[k] = (uint16_t)m;
         if (s_rid) s_rid[k] = (uint32_t)rid;
@@ -287,7 +303,7 @@ __device__ __forceinline__ void fwd_tile(int tile, const Ws &ws, const xg_camera
         if (!__syncthreads_or(!done)) break;
         // the counting variant keeps every rectangle evaluation (the work
         // count of the definition), the others skip sub-blocks out of reach
-        stage<T, NT, !COUNT, COUNT>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr,
+        stage<T, NT, !COUNT, COUNT, (COUNT || CH == 3) ? 0 : 1>(ws, vals, b0, cnt, tg, amin, s_a, s_b, s_mask, nullptr,
                                     CH == 3 ? sh.c : nullptr, COUNT ? sh.cmask : nullptr);
         __syncthreads();
         if (!__any(!done)) continue;
@@ -557,7 +573,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         const int b0 = max(end - B, 0);
         const int cnt = end - b0;
         __syncthreads();
-        stage<T, NT, true>(ws, vals, s + (uint32_t)b0, cnt, tg, amin, s_a, s_b, s_mask, s_rid);
+        stage<T, NT, true, false, 2>(ws, vals, s + (uint32_t)b0, cnt, tg, amin, s_a, s_b, s_mask, s_rid);
         __syncthreads();
         if (b0 >= wmax) continue;
         const int nl = wave_list(s_mask, min(cnt, wmax - b0), w, list);
