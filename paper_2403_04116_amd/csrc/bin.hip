@@ -12,7 +12,8 @@
 //      view), the number of pairs of each tile (LDS atomics over the items'
 //      tile rectangles) -> one row of bin_cnt;
 //   2. k_bin_columns: down each (view, tile) column of bin_cnt, the
-//      exclusive scan over the view's partitions, and the tile's total;
+//      exclusive scan over the view's partitions (four segments in parallel),
+//      and the tile's total;
 //   3. k_bin_starts: per view, the exclusive scan of the tile totals from
 //      the view's first pair slot -> the tile ranges [start, end);
 //   4. k_bin_scatter: per partition, the pairs in windows of kBinWindow
@@ -79,24 +80,53 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(Ws ws, const xg_cam
     for (int t = threadIdx.x; t < b.tiles; t += kCountThreads) row[t] = cnt[t];
 }
 
-// One thread per (view, local tile): exclusive scan down the column of the
-// view's partitions (rewritten in place); the total goes to the tile's
-// range start word until k_bin_starts replaces it.
-constexpr int kColThreads = 256;
+// Exclusive scan down each (view, local tile) column of bin_cnt over the
+// view's partitions, rewritten in place; the column total goes to the
+// tile's range start word until k_bin_starts replaces it.  A workgroup
+// takes 64 columns; its four wavefronts split each column's partitions into
+// four consecutive segments: each sums its segment, the segment totals are
+// scanned through LDS, and each rewrites its segment from its offset.
+constexpr int kColTiles = 64;
+constexpr int kColSegs = 4;
+constexpr int kColThreads = kColTiles * kColSegs;
 
 __global__ __launch_bounds__(kColThreads) void k_bin_columns(Ws ws, const xg_camera *cams, int tile,
                                                              int chunks) {
+    __shared__ uint32_t part[kColSegs][kColTiles];
     const int v = blockIdx.x / chunks;
-    const int t = (blockIdx.x - v * chunks) * kColThreads + threadIdx.x;
+    const int seg = threadIdx.x / kColTiles;
+    const int t = (blockIdx.x - v * chunks) * kColTiles + (threadIdx.x % kColTiles);
     const xg_camera &c = cams[v];
     const int tiles = ((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
-    if (t >= tiles) return;
     const int64_t stride = ws.bin_tiles;
+    const int per = (ws.bin_ppv + kColSegs - 1) / kColSegs;
+    const int q0 = min(seg * per, ws.bin_ppv), q1 = min(q0 + per, ws.bin_ppv);
     uint32_t *col = ws.bin_cnt + (int64_t)v * ws.bin_ppv * stride + t;
-    uint32_t run = 0;
-    int q = 0;
-    // eight loads in flight per step
-    for (; q + 8 <= ws.bin_ppv; q += 8) {
+    const bool live = t < tiles;
+    uint32_t sum = 0;
+    if (live) {
+        int q = q0;
+        for (; q + 8 <= q1; q += 8) {   // eight loads in flight per step
+            uint32_t x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = col[(int64_t)(q + k) * stride];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += x[k];
+        }
+        for (; q < q1; ++q) sum += col[(int64_t)q * stride];
+    }
+    part[seg][threadIdx.x % kColTiles] = sum;
+    __syncthreads();
+    if (!live) return;
+    uint32_t run = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kColSegs; ++k) {
+        const uint32_t x = part[k][threadIdx.x % kColTiles];
+        run += k < seg ? x : 0u;
+        total += x;
+    }
+    int q = q0;
+    for (; q + 8 <= q1; q += 8) {
         uint32_t x[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[k] = col[(int64_t)(q + k) * stride];
@@ -106,12 +136,12 @@ __global__ __launch_bounds__(kColThreads) void k_bin_columns(Ws ws, const xg_cam
             run += x[k];
         }
     }
-    for (; q < ws.bin_ppv; ++q) {
+    for (; q < q1; ++q) {
         const uint32_t x = col[(int64_t)q * stride];
         col[(int64_t)q * stride] = run;
         run += x;
     }
-    ws.ranges[2 * ((int64_t)c.tile_offset + t)] = run;
+    if (seg == kColSegs - 1) ws.ranges[2 * ((int64_t)c.tile_offset + t)] = total;
 }
 
 // One workgroup per view: tile ranges from the tile totals.  The view's
@@ -305,7 +335,7 @@ hipError_t launch_bin_lists(const Ws &ws, const xg_camera *cams, const Params &p
     if (parts > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned np = (unsigned)parts;
     hipLaunchKernelGGL(k_bin_count, dim3(np), dim3(kCountThreads), 0, s, ws, cams, p.tile);
-    const int chunks = (ws.bin_tiles + kColThreads - 1) / kColThreads;
+    const int chunks = (ws.bin_tiles + kColTiles - 1) / kColTiles;
     hipLaunchKernelGGL(k_bin_columns, dim3((unsigned)(ws.n_views * chunks)), dim3(kColThreads), 0, s, ws,
                        cams, p.tile, chunks);
     hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)ws.n_views), dim3(kStartThreads), 0, s, ws, cams, p.tile);

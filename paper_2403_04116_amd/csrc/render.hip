@@ -116,31 +116,25 @@ __device__ __forceinline__ uint32_t subblock_mask(int xl, int xh, int yl, int yh
 }
 
 // Smallest value over the box [X0, X1] x [Y0, Y1] of the exponent
-// E(dx, dy) = (qa dx + qb dy)^2 + (qc dy)^2 (qa > 0, qb^2 + qc^2 > 0):
-// zero when the box holds the centre, else the least of the minima along
-// its four edges (each a one-dimensional quadratic, clamped to the edge).
-__device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, float X0, float X1,
-                                                  float Y0, float Y1) {
-    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
-    float best = __builtin_inff();
-    const float ys[2] = {Y0, Y1};
-    const float xs[2] = {X0, X1};
-    // approximate reciprocals: an argmin off by a rounding error raises the
-    // minimum by a second-order amount, far inside the caller's margin
-    const float rx = qb * __builtin_amdgcn_rcpf(qa);
-    const float ry = qa * qb * __builtin_amdgcn_rcpf(qb * qb + qc * qc);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float Y = ys[k];
-        const float x = fminf(fmaxf(-rx * Y, X0), X1);
-        const float e1 = qa * x + qb * Y, e2 = qc * Y;
-        best = fminf(best, e1 * e1 + e2 * e2);
-        const float X = xs[k];
-        const float y = fminf(fmaxf(-ry * X, Y0), Y1);
-        const float f1 = qa * X + qb * y, f2 = qc * y;
-        best = fminf(best, f1 * f1 + f2 * f2);
-    }
-    return best;
+// E(dx, dy) = (qa dx + qb dy)^2 + (qc dy)^2 (qa > 0, qb^2 + qc^2 > 0), whose
+// minimum 0 is at the origin.  For a box point p, the segment from p to the
+// origin leaves the box through an edge facing the origin, at a point q
+// with E(q) <= E(p) (E is convex); so the minimum lies on the vertical edge
+// x = Xn and the horizontal edge y = Yn nearest the origin, Xn and Yn the
+// origin's coordinates clamped to the box (a clamped coordinate that the
+// box already spans gives a line through the box, whose minimum is no
+// smaller, and for a box holding the origin both lines give 0).  Along each
+// line E is a one-dimensional quadratic minimised at -rx Yn resp. -ry Xn
+// (rx = qb / qa, ry = qa qb / (qb^2 + qc^2)), clamped to the edge.
+__device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, float rx, float ry,
+                                                  float X0, float X1, float Y0, float Y1) {
+    const float xn = fminf(fmaxf(0.0f, X0), X1);
+    const float yn = fminf(fmaxf(0.0f, Y0), Y1);
+    const float x = fminf(fmaxf(-rx * yn, X0), X1);
+    const float e1 = qa * x + qb * yn, e2 = qc * yn;
+    const float y = fminf(fmaxf(-ry * xn, Y0), Y1);
+    const float f1 = qa * xn + qb * y, f2 = qc * y;
+    return fminf(e1 * e1 + e2 * e2, f1 * f1 + f2 * f2);
 }
 
 // Stages list entries [b0, b0 + cnt) of the tile into LDS, with the mask of
@@ -190,6 +184,12 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
             m = gmask[b0 + k];
         } else if (CULL || DUAL) {
             const float thr = __builtin_amdgcn_logf(rb.y * __builtin_amdgcn_rcpf(amin)) * 1.00001f + 1e-3f;
+            // the edge minimisers' slopes, with approximate reciprocals: an
+            // argmin off by a rounding error raises the minimum by a
+            // second-order amount, far inside the margin of thr
+            const float qa = ra.z, qb = ra.w, qc = rb.x;
+            const float rx = qb * __builtin_amdgcn_rcpf(qa);
+            const float ry = qa * qb * __builtin_amdgcn_rcpf(qb * qb + qc * qc);
             // pixel centres relative to the Gaussian centre
             const float ox = (float)(tg.x0 - tg.rx) + 0.5f - ux;
             const float oy = (float)(tg.y0 - tg.ry) + 0.5f - uy;
@@ -199,7 +199,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
                 const int bx = (sb % SB) * 8, by = (sb / SB) * 8;
                 const float X0 = ox + (float)max(xl, bx), X1 = ox + (float)min(xh, bx + 7);
                 const float Y0 = oy + (float)max(yl, by), Y1 = oy + (float)min(yh, by + 7);
-                if (box_min_exponent(ra.z, ra.w, rb.x, X0, X1, Y0, Y1) > thr) mc &= ~(1u << sb);
+                if (box_min_exponent(qa, qb, qc, rx, ry, X0, X1, Y0, Y1) > thr) mc &= ~(1u << sb);
             }
             if (CULL) m = mc;
             if (DUAL) s_cmask[k] = (uint16_t)mc;
