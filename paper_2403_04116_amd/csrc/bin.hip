@@ -180,8 +180,10 @@ __global__ __launch_bounds__(kStartThreads) void k_bin_starts(Ws ws, const xg_ca
 // into each wavefront's offset inside the window, and every pair lands at
 // base[tile] + that offset + its rank, where base[tile] = the tile's start
 // + the column prefix of the partition + the window's predecessors.
+// (16 wavefronts: at most 64 registers, so that two workgroups share a CU)
 template <int LT, int NW>
-__global__ __launch_bounds__(NW * kWave) void k_bin_scatter(Ws ws, const xg_camera *cams, int tile) {
+__global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws ws, const xg_camera *cams,
+                                                                              int tile) {
     constexpr int NT = NW * kWave;
     constexpr int LB = LT <= 1024 ? 10 : 12;
     constexpr int kRows = kBinWindow / NT;         // rows of 64 slots per wavefront
@@ -192,6 +194,10 @@ __global__ __launch_bounds__(NW * kWave) void k_bin_scatter(Ws ws, const xg_came
     __shared__ uint32_t base[LT];
     __shared__ uint16_t s_lt[kBinWindow];
     __shared__ uint32_t s_gi[kBinWindow];
+    // ranking: per wavefront, a 64-bit lane mask for each value of a tile's
+    // low kHashBits bits (zero between rows)
+    constexpr int kHashBits = 7, kHash = 1 << kHashBits;
+    __shared__ uint64_t s_tab[NW][kHash];
 
     if (ws.hdr->status != XG_OK) return;
     const BinPart b = bin_part(ws, cams, tile);
@@ -200,6 +206,7 @@ __global__ __launch_bounds__(NW * kWave) void k_bin_scatter(Ws ws, const xg_came
     const uint32_t E = ws.offsets[b.j1 - 1] + ws.icounts[b.j1 - 1];
     if (S == E) return;
 
+    for (int k = threadIdx.x; k < NW * kHash; k += NT) (&s_tab[0][0])[k] = 0ull;
     const uint32_t *colp = ws.bin_cnt + (int64_t)blockIdx.x * ws.bin_tiles;
     for (int t = threadIdx.x; t < b.tiles; t += NT)
         base[t] = ws.ranges[2 * ((int64_t)b.toff + t)] + colp[t];
@@ -265,7 +272,15 @@ __global__ __launch_bounds__(NW * kWave) void k_bin_scatter(Ws ws, const xg_came
             const bool valid = slot < wn;
             const uint32_t t = valid ? s_lt[slot] : 0u;
             tl[r] = t;
-            const uint64_t peers = match_peers<LB>(t, valid);
+            // lanes of the row with this tile: the lanes whose low kHashBits
+            // agree (one bit each, OR-ed into this wavefront's table slot,
+            // read back, then cleared; a wavefront's LDS operations complete
+            // in order) that also agree in the high bits (one ballot each)
+            uint64_t *slotp = &s_tab[w][t & (kHash - 1)];
+            if (valid) atomicOr(reinterpret_cast<unsigned long long *>(slotp), 1ull << lane);
+            const uint64_t same_low = *slotp;
+            *slotp = 0ull;
+            const uint64_t peers = valid ? same_low & match_peers<LB - kHashBits>(t >> kHashBits, valid) : 0ull;
             const int leader = __ffsll((unsigned long long)peers) - 1;
             uint32_t old = 0;
             if (valid && lane == leader) {
