@@ -72,6 +72,7 @@ struct ItemSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.item_blocks; }
     static constexpr int kThreads = kItemSortThreads, kItems = kItemSortItems;
     static constexpr bool kHasVal = true;
+    static constexpr bool kTabRank = true;   // LDS lane-mask table for the ranking (see k_onesweep)
     // sorted within each view: the items of view v stay in [v n, (v + 1) n)
     static constexpr bool kSegmented = true;
     static __device__ __forceinline__ int64_t seg_len(const Ws &ws) { return ws.n; }
@@ -114,6 +115,7 @@ struct PairSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPairSortThreads, kItems = kPairSortItems;
     static constexpr bool kHasVal = true;
+    static constexpr bool kTabRank = false;  // its keys and values fill the LDS
     static constexpr bool kSegmented = false;
     static __device__ __forceinline__ int64_t seg_len(const Ws &) { return 0; }
     static constexpr bool kGatherCounts = false;
@@ -143,6 +145,7 @@ struct PackedPairSort {
     static __device__ __forceinline__ int blocks(const Ws &ws) { return ws.pair_blocks; }
     static constexpr int kThreads = kPackedSortThreads, kItems = kPackedSortItems;
     static constexpr bool kHasVal = false;
+    static constexpr bool kTabRank = true;
     static constexpr bool kSegmented = false;
     static __device__ __forceinline__ int64_t seg_len(const Ws &) { return 0; }
     static constexpr bool kGatherCounts = false;
@@ -289,6 +292,9 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     using Val = typename S::Val;
     __shared__ Val svals[S::kHasVal ? kSortBlock : 1];
     __shared__ uint32_t whist[kSortThreads / kWave][kRadix];
+    // kTabRank: per wavefront and digit, the 64-bit mask of the row's lanes
+    // holding that digit (zero between rows)
+    __shared__ uint64_t stab[S::kTabRank ? kSortThreads / kWave : 1][S::kTabRank ? kRadix : 1];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t goff[kRadix];
     __shared__ uint32_t scan_lds[kSortThreads / kWave + 1];
@@ -330,6 +336,9 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
     if (threadIdx.x == 0) s_part = (int)atomicAdd(&ws.pctr[pass * kGhStride], 1u);
     for (int i = threadIdx.x; i < (kSortThreads / kWave) * kRadix; i += kSortThreads)
         (&whist[0][0])[i] = 0;
+    if constexpr (S::kTabRank)
+        for (int i = threadIdx.x; i < (kSortThreads / kWave) * kRadix; i += kSortThreads)
+            (&stab[0][0])[i] = 0ull;
     __syncthreads();
     const int64_t part = s_part;
     if (part >= parts) return;
@@ -363,7 +372,20 @@ __global__ __launch_bounds__(S::kThreads) void k_onesweep(Ws ws, int pass, int p
         const int64_t j = wbase + (int64_t)r * kWave + lane;
         const bool valid = j < send;
         const uint32_t d = S::digit(key[r], c, shift);
-        const uint64_t peers = match_peers<kRadixBits>(d, valid);
+        // lanes of the row with this digit: each valid lane ORs its bit into
+        // the digit's slot of this wavefront's table, reads the slot back,
+        // and every lane clears its slot (a wavefront's LDS operations
+        // complete in order); or one ballot per digit bit
+        uint64_t peers;
+        if constexpr (S::kTabRank) {
+            uint64_t *sp = &stab[w][d];
+            if (valid) atomicOr(reinterpret_cast<unsigned long long *>(sp), 1ull << lane);
+            const uint64_t got = *sp;
+            *sp = 0ull;
+            peers = valid ? got : 0ull;
+        } else {
+            peers = match_peers<kRadixBits>(d, valid);
+        }
         uint32_t old = 0;
         const int leader = __ffsll((unsigned long long)peers) - 1;
         if (valid && lane == leader) old = atomicAdd(&whist[w][d], (uint32_t)__popcll(peers));
