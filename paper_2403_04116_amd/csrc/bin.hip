@@ -18,9 +18,9 @@
 //      the view's first pair slot -> the tile ranges [start, end);
 //   4. k_bin_scatter: per partition, the pairs in windows of kBinWindow
 //      slots: emitted into LDS in slot order, ranked stably within the
-//      window by wavefront ballots on the tile id (per-wavefront counters,
-//      then a prefix over the wavefronts), and written at tile start +
-//      column prefix + rank.
+//      window (each row of 64 slots matched by tile through an LDS table of
+//      lane masks, per-wavefront counters, then a prefix over the
+//      wavefronts), and written at tile start + column prefix + rank.
 // The result is the same (tile, depth, index) order as the radix sort of
 // the pairs, element for element; no pair is read back from memory.
 #include "common.h"
@@ -174,8 +174,9 @@ __global__ __launch_bounds__(kStartThreads) void k_bin_starts(Ws ws, const xg_ca
 // Stable ranking and placement of one partition's pairs.  NW wavefronts;
 // LT = the most view-local tiles supported (LB bits).  Per window: the
 // pairs of slots [w0, w0 + kBinWindow) are emitted into LDS in slot order;
-// wavefront w ranks its kBinWindow / NW consecutive slots, row by row, with
-// a 16-bit counter per tile (two per word, LDS atomics from one leader lane
+// wavefront w ranks its kBinWindow / NW consecutive slots, row by row (the
+// lanes of a row holding a tile found through the lane-mask table), with a
+// 16-bit counter per tile (two per word, LDS atomics from one leader lane
 // per tile in a row); a prefix over the wavefronts then turns the counters
 // into each wavefront's offset inside the window, and every pair lands at
 // base[tile] + that offset + its rank, where base[tile] = the tile's start

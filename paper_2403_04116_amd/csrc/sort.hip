@@ -18,9 +18,10 @@
 // Each sort is one histogram launch (the digit counts of every pass in one
 // read of the keys) and one launch per 8-bit pass, in the single-pass
 // ("onesweep") form: a workgroup takes the next partition (8192 items or
-// 16384 pairs) from an
-// atomic counter, ranks its keys stably with wavefront ballots, publishes
-// its per-digit counts, stages its keys digit-sorted in LDS, reads the
+// 16384 pairs) from an atomic counter, ranks its keys stably (rows of 64
+// keys matched by digit through a per-wavefront LDS table of lane masks,
+// or by ballots), publishes its per-digit counts, stages its keys
+// digit-sorted in LDS, reads the
 // running prefix of the partitions before it from their published words
 // (decoupled look-back: a partition waits only on ones that started before
 // it, and those publish their counts without waiting, so it always
