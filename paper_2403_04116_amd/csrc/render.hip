@@ -472,39 +472,122 @@ constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRowRor8 = 0x128;   // row_ror:8
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 
-// Sum of 7 per-lane values over the wavefront, transposed so that every
-// step halves the number of live values: afterwards the lanes whose bits
-// 0..2 are zero hold the total of value q = lane >> 3 for q < 7 (lanes
-// 56-63 hold a copy of value 3).  All steps are VALU (gfx950 permlane
-// swaps and DPP), no LDS traffic.
-__device__ __forceinline__ float wave_reduce7(float v[7]) {
+// Wavefront sums of the 7 gradient terms of G list entries (acc[e][q]),
+// halving the live values at every step (reduce-scatter).  The steps over
+// lane bits 5 and 4 swap wavefront halves and rows (gfx950 permlane swaps:
+// one swap and one add per pair of values), the lower bits read a partner
+// lane through DPP (two selects and one add per pair).  All VALU, no LDS
+// traffic.  Afterwards the lane map of RedLanes<G> tells which lanes hold
+// which total; a value without a partner at some step is summed in both
+// halves and its upper copy is dropped.
+//   G = 1: 19 instructions, lane 8q holds value q (q < 7);
+//   G = 2: 33 instructions, lane 32e + 4q holds value q of entry e;
+//   G = 4: 62 instructions, lane 16e + 2q holds value q of entry e.
+template <int G>
+struct RedLanes {
+    static_assert(G == 1 || G == 2 || G == 4, "groups of 1, 2 or 4 entries");
+    static constexpr int kEShift = G == 4 ? 4 : 5;   // entry = lane >> kEShift (G > 1)
+    static constexpr int kQShift = G == 4 ? 1 : (G == 2 ? 2 : 3);
+    __device__ static int entry(int lane) { return G == 1 ? 0 : lane >> kEShift; }
+    __device__ static int word(int lane) { return (lane >> kQShift) & 7; }
+    __device__ static bool adds(int lane) {
+        return (lane & ((1 << kQShift) - 1)) == 0 && word(lane) < 7;
+    }
+};
+
+__device__ __forceinline__ float wave_reduce_group(const float (&acc)[1][7]) {
     const int lane = lane_id();
+    float v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        // lanes 0-31 end with value k summed over lane pairs (l, l+32),
-        // lanes 32-63 with value k+4 (value 3 again for k = 3: the swap of a
-        // value with itself leaves its pair sums in both halves)
-        const float hi = k < 3 ? v[k + 4] : v[3];
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(hi),
+        // lanes 0-31 keep value k, lanes 32-63 value k + 4 (value 3 twice)
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[0][k]),
+                                                        __float_as_uint(acc[0][k < 3 ? k + 4 : 3]),
                                                         false, false);
         v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        // within each half: even rows keep value k, odd rows value k+2
+        // even rows keep v[k], odd rows v[k + 2]
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 2]),
                                                         false, false);
         v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    const bool hi = lane & 8;
-    const float mine = hi ? v[1] : v[0];
-    const float other = hi ? v[0] : v[1];
-    float x = mine + XG_DPP(other, kDppRowRor8);
+    const bool h3 = lane & 8;
+    float x = (h3 ? v[1] : v[0]) + XG_DPP(h3 ? v[0] : v[1], kDppRowRor8);
     x += XG_DPP(x, kDppQuadXor1);
     x += XG_DPP(x, kDppQuadXor2);
     x += XG_DPP(x, kDppHalfMirror);
     return x;
 }
+
+__device__ __forceinline__ float wave_reduce_group(const float (&acc)[2][7]) {
+    const int lane = lane_id();
+    float b[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        // lanes 0-31 keep entry 0, lanes 32-63 entry 1: b[q]
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[0][i]), __float_as_uint(acc[1][i]),
+                                                        false, false);
+        b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float c[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        // even rows keep q = i, odd rows q = i + 4 (q = 3 twice)
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[i]), __float_as_uint(b[i < 3 ? i + 4 : 3]),
+                                                        false, false);
+        c[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool h3 = lane & 8, h2 = lane & 4;
+    float d[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        d[j] = (h3 ? c[j + 2] : c[j]) + XG_DPP(h3 ? c[j] : c[j + 2], kDppRowRor8);
+    float x = (h2 ? d[1] : d[0]) + XG_DPP(h2 ? d[0] : d[1], kDppHalfMirror);
+    x += XG_DPP(x, kDppQuadXor2);
+    x += XG_DPP(x, kDppQuadXor1);
+    return x;
+}
+
+__device__ __forceinline__ float wave_reduce_group(const float (&acc)[4][7]) {
+    const int lane = lane_id();
+    float b[14];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) {
+        // flat index f = 7e + q: lanes 0-31 keep f = i, lanes 32-63 f = i + 14
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[i / 7][i % 7]),
+                                                        __float_as_uint(acc[(i + 14) / 7][(i + 14) % 7]),
+                                                        false, false);
+        b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float c[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        // even rows keep f = i, odd rows f = i + 7: c[q] is value q of entry lane >> 4
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[i]), __float_as_uint(b[i + 7]),
+                                                        false, false);
+        c[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    // lane bit 3 selects q = i or i + 4 (q = 3 twice)
+    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2;
+    float d[4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        d[i] = (h3 ? c[i + 4] : c[i]) + XG_DPP(h3 ? c[i] : c[i + 4], kDppRowRor8);
+    d[3] = c[3] + XG_DPP(c[3], kDppRowRor8);
+    // lane bit 2 selects d[j] or d[j + 2] (the mirror partner has bit 2 flipped)
+    float e[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        e[j] = (h2 ? d[j + 2] : d[j]) + XG_DPP(h2 ? d[j] : d[j + 2], kDppHalfMirror);
+    float x = (h1 ? e[1] : e[0]) + XG_DPP(h1 ? e[0] : e[1], kDppQuadXor2);
+    x += XG_DPP(x, kDppQuadXor1);
+    return x;
+}
+
+// List entries whose gradient terms are summed over the wavefront together.
+constexpr int kBwdGroup = 2;
 
 template <int T, int B, bool STORE>
 __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera *cams,
@@ -567,8 +650,12 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     wmax = __builtin_amdgcn_readfirstlane(wmax);
 
     float R = 0.0f;   // intensity behind, seen from just after the current Gaussian
-    // the gradient word this lane adds (lanes 8q, q < 7, add value q of an entry)
-    float *g2q = ws.grad2d + (lane >> 3);
+    // the lanes that add a reduced total: entry e of the group, gradient word q
+    constexpr int G = kBwdGroup;
+    const int lane_e = RedLanes<G>::entry(lane);
+    const int lane_q = RedLanes<G>::word(lane);
+    const bool lane_adds = RedLanes<G>::adds(lane);
+    float *g2q = ws.grad2d + lane_q;
     for (int end = bmax; end > 0; end -= B) {
         const int b0 = max(end - B, 0);
         const int cnt = end - b0;
@@ -594,8 +681,15 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
           uint32_t off_n = (iw[3] >> 16) & kOffMask;
           float4 sa_n = slot16(s_a, off_n);
           float4 sb_n = slot16(s_b, off_n);
+          // the 7 gradient terms of G consecutive entries, summed over the
+          // wavefront together; entries that no lane contributes to add zeros
+          // and are left out of the atomics (bit e of live4)
+          float acc[G][7];
+          uint32_t live4 = 0;
+          int rid = 0;   // Gaussian record of entry lane_e
 #pragma unroll
           for (int u = 7; u >= 0; --u) {
+            const int e = u & (G - 1);
             const uint32_t off = off_n;   // 16 x batch index
             const float4 sa = sa_n;
             const float4 sb = sb_n;
@@ -604,45 +698,53 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                 sa_n = slot16(s_a, off_n);
                 sb_n = slot16(s_b, off_n);
             }
-            if (j0 + u >= nl) continue;
-            const bool inr = (int)off <= lastk16 && in_rect<T>(__float_as_uint(sb.w), rkey, lx, ly);
+            const bool inr = j0 + u < nl && (int)off <= lastk16 &&
+                             in_rect<T>(__float_as_uint(sb.w), rkey, lx, ly);
             const Eval ev = splat_eval(sa, sb, pxr, pyr, amax);
             const bool act = inr && ev.alpha >= amin;
-            if (!__any(act)) continue;
-            // Every lane runs the same arithmetic; a lane that is not a
-            // contributor gets a zero upstream gradient (exact zeros in the
-            // reduction) and keeps its transmittance and R.
-            const float om = 1.0f - ev.alpha;
-            float Tj;   // T before this Gaussian
-            if (STORE) {
-                Tj = act ? (c < ts.slots ? tnext : Tr * __builtin_amdgcn_rcpf(om)) : Tr;
-                const int cn = act ? c - 1 : c;
-                if (act && cn >= 0 && cn < ts.slots) tnext = tbase[(int64_t)cn * NT];
-                c = cn;
+            if (__any(act)) {
+                // Every lane runs the same arithmetic; a lane that is not a
+                // contributor gets a zero upstream gradient (exact zeros in the
+                // reduction) and keeps its transmittance and R.
+                const float om = 1.0f - ev.alpha;
+                float Tj;   // T before this Gaussian
+                if (STORE) {
+                    Tj = act ? (c < ts.slots ? tnext : Tr * __builtin_amdgcn_rcpf(om)) : Tr;
+                    const int cn = act ? c - 1 : c;
+                    if (act && cn >= 0 && cn < ts.slots) tnext = tbase[(int64_t)cn * NT];
+                    c = cn;
+                } else {
+                    Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;
+                }
+                const float ge = act ? g : 0.0f;
+                const float it = sb.z;
+                const float gT = ge * Tj;
+                float *v = acc[e];
+                v[6] = gT * ev.alpha;                          // dL/d intensity
+                const float galpha = gT * (it - R);            // dL/d alpha
+                R = act ? fmaf(it, ev.alpha, om * R) : R;
+                Tr = Tj;
+                const float ga = (ev.a > amax) ? 0.0f : galpha;
+                v[5] = ga * ev.G;                              // dL/d opacity
+                const float gp = ga * ev.a;                    // dL/d power, power = -d^T Q d / 2
+                // moments of gp over the pixel offsets d = pixel - u; the inverse
+                // covariance is applied once per (view, Gaussian)
+                v[0] = gp * ev.dx;
+                v[1] = gp * ev.dy;
+                v[2] = v[0] * ev.dx;
+                v[3] = v[0] * ev.dy;
+                v[4] = v[1] * ev.dy;
+                if (lane_e == e) rid = (int)s_rid[off >> 4];
+                live4 |= 1u << e;
             } else {
-                Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) acc[e][q] = 0.0f;
             }
-            const float ge = act ? g : 0.0f;
-            const float it = sb.z;
-            const float gT = ge * Tj;
-            float v[7];
-            v[6] = gT * ev.alpha;                          // dL/d intensity
-            const float galpha = gT * (it - R);            // dL/d alpha
-            R = act ? fmaf(it, ev.alpha, om * R) : R;
-            Tr = Tj;
-            const float ga = (ev.a > amax) ? 0.0f : galpha;
-            v[5] = ga * ev.G;                              // dL/d opacity
-            const float gp = ga * ev.a;                    // dL/d power, power = -d^T Q d / 2
-            // moments of gp over the pixel offsets d = pixel - u; the inverse
-            // covariance is applied once per (view, Gaussian)
-            v[0] = gp * ev.dx;
-            v[1] = gp * ev.dy;
-            v[2] = v[0] * ev.dx;
-            v[3] = v[0] * ev.dy;
-            v[4] = v[1] * ev.dy;
-            const float x = wave_reduce7(v);
-            const int q = lane >> 3;
-            if ((lane & 7) == 0 && q < 7) atomicAdd(g2q + 8 * (int64_t)s_rid[off >> 4], x);
+            if (e == 0 && live4 != 0) {
+                const float x = wave_reduce_group(acc);
+                if (lane_adds && ((live4 >> lane_e) & 1u)) atomicAdd(g2q + 8 * (int64_t)rid, x);
+                live4 = 0;
+            }
           }
         }
     }
