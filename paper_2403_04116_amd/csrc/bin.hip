@@ -20,7 +20,9 @@
 //      slots: emitted into LDS in slot order, ranked stably within the
 //      window (each row of 64 slots matched by tile through an LDS table of
 //      lane masks, per-wavefront counters, then a prefix over the
-//      wavefronts), and written at tile start + column prefix + rank.
+//      wavefronts), reordered in LDS so that each tile's pairs are
+//      adjacent, and written at tile start + column prefix + rank (runs of
+//      consecutive entries per tile, not one scattered word per pair).
 // The result is the same (tile, depth, index) order as the radix sort of
 // the pairs, element for element; no pair is read back from memory.
 #include "common.h"
@@ -178,9 +180,12 @@ __global__ __launch_bounds__(kStartThreads) void k_bin_starts(Ws ws, const xg_ca
 // lanes of a row holding a tile found through the lane-mask table), with a
 // 16-bit counter per tile (two per word, LDS atomics from one leader lane
 // per tile in a row); a prefix over the wavefronts then turns the counters
-// into each wavefront's offset inside the window, and every pair lands at
+// into each wavefront's offset inside the window.  Every pair belongs at
 // base[tile] + that offset + its rank, where base[tile] = the tile's start
-// + the column prefix of the partition + the window's predecessors.
+// + the column prefix of the partition + the window's predecessors; the
+// pairs are first permuted in LDS into blocks of one tile each (a
+// wavefront scan of the tile totals), so that the stores of a row write
+// runs of consecutive list entries.
 // (16 wavefronts: at most 64 registers, so that two workgroups share a CU)
 template <int LT, int NW>
 __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws ws, const xg_camera *cams,
@@ -195,9 +200,14 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
     __shared__ uint32_t base[LT];
     __shared__ uint16_t s_lt[kBinWindow];
     __shared__ uint32_t s_gi[kBinWindow];
+    // the window's slots in tile order (slot of each window position), and
+    // each tile's first window position (two 16-bit starts per word)
+    __shared__ uint16_t s_perm[kBinWindow];
+    __shared__ uint32_t s_lst[LT / 2];
+    __shared__ uint32_t s_alloc;
     // ranking: per wavefront, a 64-bit lane mask for each value of a tile's
     // low kHashBits bits (zero between rows)
-    constexpr int kHashBits = 7, kHash = 1 << kHashBits;
+    constexpr int kHashBits = 6, kHash = 1 << kHashBits;
     __shared__ uint64_t s_tab[NW][kHash];
 
     if (ws.hdr->status != XG_OK) return;
@@ -214,22 +224,27 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
 
     // this thread's items: slot range, view-local tile rectangle, index
     const int sel = ws.hdr->item_sel & 1;
-    uint32_t i_off[kMyItems], i_cnt[kMyItems], i_gi[kMyItems];
-    TileRect i_r[kMyItems];
+    // (a view has at most kBinMaxTiles tiles: counts and tile coordinates
+    // fit 16 bits)
+    uint32_t i_off[kMyItems], i_gi[kMyItems];
+    uint32_t i_cy[kMyItems];  // pair count | first tile row << 16
+    uint32_t i_x[kMyItems];   // first | last tile column << 16
 #pragma unroll
     for (int k = 0; k < kMyItems; ++k) {
         const int64_t j = b.j0 + (int64_t)k * NT + threadIdx.x;
-        i_cnt[k] = 0;
+        i_cy[k] = 0;
         i_off[k] = 0;
         i_gi[k] = 0;
-        i_r[k] = TileRect{0, 0, 0, 0};
+        i_x[k] = 0;
         if (j < b.j1) {
-            i_cnt[k] = ws.icounts[j];
-            if (i_cnt[k] > 0) {
+            const uint32_t cnt = ws.icounts[j];
+            if (cnt > 0) {
                 const uint64_t val = ws.ivals[sel][j];
                 i_off[k] = ws.offsets[j];
                 i_gi[k] = (uint32_t)val - (uint32_t)b.view * (uint32_t)ws.n;
-                i_r[k] = item_tile_rect(ws, val, tile);
+                const TileRect r = item_tile_rect(ws, val, tile);
+                i_x[k] = (uint32_t)r.tx0 | ((uint32_t)r.tx1 << 16);
+                i_cy[k] = cnt | ((uint32_t)r.ty0 << 16);
             }
         }
     }
@@ -245,34 +260,36 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
         const uint32_t w1 = min(E, w0 + (uint32_t)kBinWindow);
         const int wn = (int)(w1 - w0);
         for (int k = threadIdx.x; k < NW * (LT / 2); k += NT) (&h16[0][0])[k] = 0u;
+        if (threadIdx.x == 0) s_alloc = 0u;
         // emission: each item writes its pairs inside the window, row-major
         // over its rectangle
 #pragma unroll
         for (int k = 0; k < kMyItems; ++k) {
-            const uint32_t a = max(i_off[k], w0), e = min(i_off[k] + i_cnt[k], w1);
-            if (i_cnt[k] == 0 || a >= e) continue;
-            const uint32_t rw = (uint32_t)(i_r[k].tx1 - i_r[k].tx0 + 1);
+            const uint32_t cnt = i_cy[k] & 0xffffu;
+            const uint32_t a = max(i_off[k], w0), e = min(i_off[k] + cnt, w1);
+            if (cnt == 0 || a >= e) continue;
+            const int tx0 = (int)(i_x[k] & 0xffffu), tx1 = (int)(i_x[k] >> 16);
+            const uint32_t rw = (uint32_t)(tx1 - tx0 + 1);
             const uint32_t m = a - i_off[k];
-            int ty = i_r[k].ty0 + (int)(m / rw);
-            int tx = i_r[k].tx0 + (int)(m % rw);
+            int ty = (int)(i_cy[k] >> 16) + (int)(m / rw);
+            int tx = tx0 + (int)(m % rw);
             for (uint32_t s = a; s < e; ++s) {
                 s_lt[s - w0] = (uint16_t)(ty * b.tiles_x + tx);
                 s_gi[s - w0] = i_gi[k];
-                if (++tx > i_r[k].tx1) {
-                    tx = i_r[k].tx0;
+                if (++tx > tx1) {
+                    tx = tx0;
                     ++ty;
                 }
             }
         }
         __syncthreads();
         // ranking: wavefront w owns slots [w kRows 64, (w + 1) kRows 64)
-        uint32_t rank[kRows], tl[kRows];
+        uint32_t rt[kRows];   // rank in the wavefront | tile << 16 (both below 2^16)
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             const int slot = (w * kRows + r) * kWave + lane;
             const bool valid = slot < wn;
             const uint32_t t = valid ? s_lt[slot] : 0u;
-            tl[r] = t;
             // lanes of the row with this tile: the lanes whose low kHashBits
             // agree (one bit each, OR-ed into this wavefront's table slot,
             // read back, then cleared; a wavefront's LDS operations complete
@@ -289,10 +306,13 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
                 old = (atomicAdd(&h16[w][t >> 1], (uint32_t)__popcll(peers) << sh) >> sh) & 0xffffu;
             }
             old = (uint32_t)__shfl((int)old, leader < 0 ? 0 : leader, kWave);
-            rank[r] = old + (uint32_t)__popcll(peers & lt_mask);
+            rt[r] = (old + (uint32_t)__popcll(peers & lt_mask)) | (t << 16);
         }
         __syncthreads();
-        // prefix over the wavefronts, two tiles (one word) per step
+        // prefix over the wavefronts, two tiles (one word) per step; then each
+        // tile's block of window positions: a wavefront scan of the word
+        // totals and one allocation per wavefront (blocks in any order, each
+        // tile's block contiguous)
         constexpr int kPairsPerThread = (LT / 2 + NT - 1) / NT;
         uint32_t adv[kPairsPerThread];
 #pragma unroll
@@ -308,18 +328,48 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
                 }
             }
             adv[k] = run;
+            const uint32_t lo = run & 0xffffu;
+            const uint32_t tot = lo + (run >> 16);
+            uint32_t incl = tot;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t up = (uint32_t)__shfl_up((int)incl, d, kWave);
+                if (lane >= d) incl += up;
+            }
+            const uint32_t wsum = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+            uint32_t wbase = 0;
+            if (lane == 0 && wsum) wbase = atomicAdd(&s_alloc, wsum);
+            wbase = (uint32_t)__shfl((int)wbase, 0, kWave);
+            const uint32_t st = wbase + incl - tot;
+            if (tw < LT / 2 && tot) s_lst[tw] = st | ((st + lo) << 16);
         }
         __syncthreads();
-        // placement
+        // each slot's window position: its tile's block, the wavefronts
+        // before it, its rank in the wavefront
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             const int slot = (w * kRows + r) * kWave + lane;
             if (slot < wn) {
-                const uint32_t t = tl[r];
-                const uint32_t off = (h16[w][t >> 1] >> (16u * (t & 1u))) & 0xffffu;
-                const uint32_t dst = base[t] + off + rank[r];
-                const uint32_t gt = (uint32_t)b.toff + t;
+                const uint32_t t = rt[r] >> 16;
+                const uint32_t sh = 16u * (t & 1u);
+                const uint32_t off = (h16[w][t >> 1] >> sh) & 0xffffu;
+                const uint32_t st = (s_lst[t >> 1] >> sh) & 0xffffu;
+                s_perm[st + off + (rt[r] & 0xffffu)] = (uint16_t)slot;
+            }
+        }
+        __syncthreads();
+        // placement in tile order: consecutive positions of a tile go to
+        // consecutive list entries (coalesced stores)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int k = (w * kRows + r) * kWave + lane;
+            if (k < wn) {
+                const int slot = s_perm[k];
+                const uint32_t t = s_lt[slot];
                 const uint32_t gi = s_gi[slot];
+                const uint32_t st = (s_lst[t >> 1] >> (16u * (t & 1u))) & 0xffffu;
+                const uint32_t dst = base[t] + ((uint32_t)k - st);
+                const uint32_t gt = (uint32_t)b.toff + t;
                 if (dst >= (uint64_t)ws.cap) continue;   // never: the counts add up to the slots
                 if (gb) {
                     out_t[dst] = (gt << gb) | gi;
