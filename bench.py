@@ -543,7 +543,12 @@ def main():
         "loss_grad": ("hbm", LOSS_BYTES_PER_PX * npx),
         "render_bwd": ("alu", bwd_ops),
         "preprocess_bwd": ("hbm", 32 * n_items + 144 * w.n),
-        "adam": ("hbm", 12 * w.n * 30),
+        # per Gaussian: 11 raw scalars (means, log-scales, quaternion, opacity
+        # logit) read x, grad, m, v and write x, m, v (28 B), the activated
+        # scales and opacity written (16 B); per response feature read x, m, v
+        # and write them (24 B); the intensity gradient read and the new
+        # intensity written (8 B)
+        "adam": ("hbm", w.n * (11 * 28 + 16 + 24 * (opt.n_features if opt is not None else 0) + 8)),
     }
     stages = {}
     for name in STAGES:

@@ -147,38 +147,45 @@ __global__ __launch_bounds__(256) void k_adam_features(AdamArgs a) {
     float coef[3];
     if (!step_coefficients(a, coef)) return;
     const float bias1 = coef[0], bias2 = coef[1];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = t / G;
-    const int k = (int)(t % G);
-    if (i >= a.n) return;        // whole groups leave together
+    const int k = (int)(threadIdx.x % G);   // the stride is a multiple of G
     const bool own = k < nf;
     const float wk = own ? s_w[k] : 0.0f;
-    float *f = a.p.features + i * nf + k;
-    const float x = own ? *f : 0.0f;
-    float dot = wk * x;
+    // grid-stride over the groups (the weights and coefficients are set up
+    // once per workgroup); the G lanes of a group stay together
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < a.n * G;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / G;
+        float *f = a.p.features + i * nf + k;
+        const float x = own ? *f : 0.0f;
+        float dot = wk * x;
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) dot += __shfl_xor(dot, o, kWave);
-    const float s = sigmoidf(dot);
-    const float gs = a.g.intensity[i] * s * (1.0f - s);
-    float xn = 0.0f;
-    if (own) {
-        xn = adam_update(a, 11 * a.n + i * nf + k, x, gs * wk, a.c.lr_feature, bias1, bias2);
-        *f = xn;
+        for (int o = G / 2; o > 0; o >>= 1) dot += __shfl_xor(dot, o, kWave);
+        const float s = sigmoidf(dot);
+        const float gs = a.g.intensity[i] * s * (1.0f - s);
+        float xn = 0.0f;
+        if (own) {
+            xn = adam_update(a, 11 * a.n + i * nf + k, x, gs * wk, a.c.lr_feature, bias1, bias2);
+            *f = xn;
+        }
+        float dn = wk * xn;
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) dn += __shfl_xor(dn, o, kWave);
+        if (k == 0) a.intensity[i] = sigmoidf(dn);
     }
-    float dn = wk * xn;
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) dn += __shfl_xor(dn, o, kWave);
-    if (k == 0) a.intensity[i] = sigmoidf(dn);
 }
 
 __global__ void k_step_advance(int32_t *step, const int32_t *gate) {
     if (threadIdx.x == 0 && (gate == nullptr || *gate == 0)) *step += 1;
 }
 
+// Grid of a grid-stride launch of 256 threads over n work items: at most
+// 2048 workgroups (8 per CU on 256 CUs), so the per-workgroup set-up (step
+// coefficients in double, the response weights) runs a few thousand times
+// rather than once per 256 items.
 unsigned grid_of(int64_t n) {
     int64_t nb = (n + 255) / 256;
     if (nb < 1) nb = 1;
-    if (nb > 65536) nb = 65536;
+    if (nb > 2048) nb = 2048;
     return (unsigned)nb;
 }
 
@@ -211,8 +218,7 @@ hipError_t launch_adam(const xg_params &p, const xg_grads &g, float *m, float *v
     hipLaunchKernelGGL(k_adam, dim3(grid_of(11 * (int64_t)p.n)), dim3(256), 0, s, a);
     int G = 1;
     while (G < p.n_features) G *= 2;
-    const int64_t nb = ((int64_t)p.n * G + 255) / 256;
-    const dim3 grid((unsigned)(nb > 0 ? nb : 1));
+    const dim3 grid(grid_of((int64_t)p.n * G));
     switch (G) {
         case 1: hipLaunchKernelGGL(k_adam_features<1>, grid, dim3(256), 0, s, a); break;
         case 2: hipLaunchKernelGGL(k_adam_features<2>, grid, dim3(256), 0, s, a); break;
