@@ -182,15 +182,19 @@ xg_status xg_preprocess(const xg_frame *f /* [host] */, const xg_gaussians *g /*
                         void *stream);
 
 /* Stage 2 (Sec. 3.2): the per-tile lists of Gaussians sorted by camera
- * depth.  The (view, Gaussian) items are radix-sorted stably by depth on
- * the depth bits that vary; their tile counts are scanned in that order;
- * one (global tile id, Gaussian index) pair is emitted per (view,
- * Gaussian, tile) in that order; and the pairs are radix-sorted stably by
- * tile id.  A tile lists only Gaussians of its own view, so the result
- * equals a sort of the keys (tile << 32 | float32 bits of the depth), ties
- * by ascending Gaussian index.  Also fills per-tile [start, end) ranges.
- * A sort whose partitions cannot complete reports XG_EHIP in the status
- * word. */
+ * depth.  The (view, Gaussian) items of each view are radix-sorted stably
+ * by depth on the depth bits that vary, and their tile counts are scanned
+ * in that order (offsets).  One (global tile id, Gaussian index) pair per
+ * (view, Gaussian, tile) is then placed in tile order: when every view has
+ * at most 4096 tiles, directly at its list position by a stable counting
+ * sort of each view's pairs by tile; otherwise emitted in item order and
+ * radix-sorted stably by tile id.  A tile lists only Gaussians of its own
+ * view, so either way the result equals a sort of the keys (tile << 32 |
+ * float32 bits of the depth), ties by ascending Gaussian index.  Also
+ * fills the per-tile [start, end) ranges and the pair count; more pairs
+ * than the capacity raise XG_ECAPACITY (no pair is written, every range
+ * is empty).  A sort whose partitions cannot complete reports XG_EHIP in
+ * the status word. */
 xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
 
 /* Stage 3 (Eq. 10): front-to-back blending of every pixel over its tile's

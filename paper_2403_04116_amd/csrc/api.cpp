@@ -70,8 +70,8 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 
 struct Plan {
     xg_ws_layout lay;
-    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, vhist, bin_cnt, lookback[2],
-        tile_order, ssim, entry_mask;
+    size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, vhist, bin_cnt, bin_ptot,
+        bin_pstart, lookback[2], tile_order, ssim, entry_mask;
     int64_t total_px, total_tiles, n_items;
     int32_t item_blocks, pair_blocks, tile_bits, pair_passes, pair_gbits, bin_tiles, bin_ppv;
 };
@@ -127,6 +127,8 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.ghist = o;              o = align_up(o + 4 * (size_t)kSortCtlWords);
     P.vhist = o;              o = align_up(o + 4 * (size_t)f->n_views * kMaxPasses * kRadix);
     P.bin_cnt = o;            o = align_up(o + 4 * (size_t)f->n_views * P.bin_ppv * P.bin_tiles);
+    P.bin_ptot = o;           o = align_up(o + 4 * (size_t)f->n_views * P.bin_ppv);
+    P.bin_pstart = o;         o = align_up(o + 4 * (size_t)f->n_views * P.bin_ppv);
     for (int b = 0; b < 2; ++b) { P.lookback[b] = o; o = align_up(o + 8 * (size_t)lb_words); }
     L.ranges = o;             o = align_up(o + 8 * (size_t)P.total_tiles);
     P.entry_mask = o;         o = align_up(o + (f->settings.tile > 16 ? 2 : 1) * (size_t)cap);
@@ -159,6 +161,8 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.ghist = (uint32_t *)(b + P.ghist);
     w.vhist = (uint32_t *)(b + P.vhist);
     w.bin_cnt = (uint32_t *)(b + P.bin_cnt);
+    w.bin_ptot = (uint32_t *)(b + P.bin_ptot);
+    w.bin_pstart = (uint32_t *)(b + P.bin_pstart);
     w.bin_tiles = P.bin_tiles;
     w.bin_ppv = P.bin_ppv;
     w.pctr = w.ghist + kMaxPasses * kRadix * kGhStride;
@@ -326,13 +330,14 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
     hipError_t e = hipSuccess;
     if (ws.n_items > 0) {
         e = launch_sort_items(ws, s);
-        if (e == hipSuccess)
-            e = launch_scan(ws.icounts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
-                            &ws.hdr->status, ws.cap, s);
         if (ws.bin_tiles > 0) {
-            // the lists by counting (writes every tile range)
+            // the lists by counting (writes the item offsets, the pair count,
+            // the capacity status and every tile range)
             if (e == hipSuccess) e = launch_bin_lists(ws, f->cams_dev, p, s);
         } else {
+            if (e == hipSuccess)
+                e = launch_scan(ws.icounts, ws.offsets, ws.n_items, ws.scan_tmp, &ws.hdr->n_pairs,
+                                &ws.hdr->status, ws.cap, s);
             if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
             if (e == hipSuccess) e = launch_sort_pairs(ws, s);
             if (e == hipSuccess) e = launch_ranges(ws, true, s);

@@ -70,14 +70,26 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(Ws ws, const xg_cam
         n_t[k] = j < b.j1 ? ws.icounts[j] : 0u;
         val[k] = j < b.j1 ? ws.ivals[sel][j] : 0ull;
     }
+    uint32_t mine = 0;   // this thread's pairs
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         if (n_t[k] == 0) continue;
+        mine += n_t[k];
         const TileRect r = item_tile_rect(ws, val[k], tile);
         for (int ty = r.ty0; ty <= r.ty1; ++ty)
             for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&cnt[ty * b.tiles_x + tx], 1u);
     }
+    // the partition's pair total (at most kBinItems * kBinMaxTiles)
+    __shared__ uint32_t s_tot[kCountThreads / kWave];
+    for (int off = kWave / 2; off > 0; off >>= 1) mine += (uint32_t)__shfl_xor((int)mine, off, kWave);
+    if (lane_id() == 0) s_tot[threadIdx.x / kWave] = mine;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kCountThreads / kWave; ++w) tot += s_tot[w];
+        ws.bin_ptot[blockIdx.x] = tot;
+    }
     uint32_t *row = ws.bin_cnt + (int64_t)blockIdx.x * ws.bin_tiles;
     for (int t = threadIdx.x; t < b.tiles; t += kCountThreads) row[t] = cnt[t];
 }
@@ -146,18 +158,62 @@ __global__ __launch_bounds__(kColThreads) void k_bin_columns(Ws ws, const xg_cam
     if (seg == kColSegs - 1) ws.ranges[2 * ((int64_t)c.tile_offset + t)] = total;
 }
 
-// One workgroup per view: tile ranges from the tile totals.  The view's
-// pairs start at the scanned slot of its first item.  Empty tiles, and all
-// tiles once the capacity is exceeded, read (0, 0).
+// One workgroup per view.  The view's first pair slot is the sum of the
+// pair totals of the partitions of the views before it; the pair count of
+// the whole frame (every workgroup sums all partitions) is checked against
+// the capacity (XG_ECAPACITY, and the pair count, written by the first
+// workgroup).  Then the exclusive scan of the view's partition totals
+// gives each partition's first slot, and the scan of the tile totals the
+// tile ranges.  Empty tiles, and all tiles once the capacity is exceeded,
+// read (0, 0).
 constexpr int kStartThreads = 1024;
 
 __global__ __launch_bounds__(kStartThreads) void k_bin_starts(Ws ws, const xg_camera *cams, int tile) {
     __shared__ uint32_t lds[kStartThreads / kWave + 1];
+    __shared__ uint64_t s_sum[2][kStartThreads / kWave];
     const int v = blockIdx.x;
     const xg_camera &c = cams[v];
     const int tiles = ((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
-    const bool ok = ws.hdr->status == XG_OK;
-    uint32_t carry = ws.offsets[(int64_t)v * ws.n];
+    const int ppv = ws.bin_ppv;
+    const int64_t nparts = (int64_t)ws.n_views * ppv;
+    uint64_t before = 0, all = 0;
+    for (int64_t k = threadIdx.x; k < nparts; k += kStartThreads) {
+        const uint32_t x = ws.bin_ptot[k];
+        all += x;
+        if (k < (int64_t)v * ppv) before += x;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        before += __shfl_xor(before, off, kWave);
+        all += __shfl_xor(all, off, kWave);
+    }
+    if (lane_id() == 0) {
+        s_sum[0][threadIdx.x / kWave] = before;
+        s_sum[1][threadIdx.x / kWave] = all;
+    }
+    __syncthreads();
+    before = 0;
+    all = 0;
+#pragma unroll
+    for (int w = 0; w < kStartThreads / kWave; ++w) {
+        before += s_sum[0][w];
+        all += s_sum[1][w];
+    }
+    const bool ok = ws.hdr->status == XG_OK && all <= (uint64_t)ws.cap;
+    if (v == 0 && threadIdx.x == 0) {
+        ws.hdr->n_pairs = (int32_t)(all > 0x7fffffffull ? 0x7fffffffull : all);
+        if (all > (uint64_t)ws.cap) ws.hdr->status = XG_ECAPACITY;
+    }
+    // partition starts (below the capacity whenever they are used)
+    uint32_t carry = (uint32_t)before;
+    for (int q0 = 0; q0 < ppv; q0 += kStartThreads) {
+        const int q = q0 + threadIdx.x;
+        const uint32_t x = q < ppv ? ws.bin_ptot[(int64_t)v * ppv + q] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(x, lds, &tot);
+        if (q < ppv) ws.bin_pstart[(int64_t)v * ppv + q] = carry + ex;
+        carry += tot;
+    }
+    carry = (uint32_t)before;
     uint32_t *rg = ws.ranges + 2 * (int64_t)c.tile_offset;
     for (int t0 = 0; t0 < tiles; t0 += kStartThreads) {
         const int t = t0 + threadIdx.x;
@@ -213,16 +269,18 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
     if (ws.hdr->status != XG_OK) return;
     const BinPart b = bin_part(ws, cams, tile);
     if (b.j0 >= b.j1) return;
-    const uint32_t S = ws.offsets[b.j0];
-    const uint32_t E = ws.offsets[b.j1 - 1] + ws.icounts[b.j1 - 1];
-    if (S == E) return;
+    // the partition's pair slots [S, E)
+    const uint32_t S = ws.bin_pstart[blockIdx.x];
+    const uint32_t E = S + ws.bin_ptot[blockIdx.x];
 
     for (int k = threadIdx.x; k < NW * kHash; k += NT) (&s_tab[0][0])[k] = 0ull;
     const uint32_t *colp = ws.bin_cnt + (int64_t)blockIdx.x * ws.bin_tiles;
     for (int t = threadIdx.x; t < b.tiles; t += NT)
         base[t] = ws.ranges[2 * ((int64_t)b.toff + t)] + colp[t];
 
-    // this thread's items: slot range, view-local tile rectangle, index
+    // this thread's items: slot range (the exclusive scan of the item
+    // counts in item order, from S; also written to offsets), view-local
+    // tile rectangle, index
     const int sel = ws.hdr->item_sel & 1;
     // (a view has at most kBinMaxTiles tiles: counts and tile coordinates
     // fit 16 bits)
@@ -231,7 +289,7 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
     uint32_t i_x[kMyItems];   // first | last tile column << 16
 #pragma unroll
     for (int k = 0; k < kMyItems; ++k) {
-        const int64_t j = b.j0 + (int64_t)k * NT + threadIdx.x;
+        const int64_t j = b.j0 + (int64_t)threadIdx.x * kMyItems + k;
         i_cy[k] = 0;
         i_off[k] = 0;
         i_gi[k] = 0;
@@ -240,12 +298,38 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
             const uint32_t cnt = ws.icounts[j];
             if (cnt > 0) {
                 const uint64_t val = ws.ivals[sel][j];
-                i_off[k] = ws.offsets[j];
                 i_gi[k] = (uint32_t)val - (uint32_t)b.view * (uint32_t)ws.n;
                 const TileRect r = item_tile_rect(ws, val, tile);
                 i_x[k] = (uint32_t)r.tx0 | ((uint32_t)r.tx1 << 16);
                 i_cy[k] = cnt | ((uint32_t)r.ty0 << 16);
             }
+        }
+    }
+    {
+        // a thread's items are consecutive (j0 + thread kMyItems + k): one
+        // wavefront scan of the thread sums, the wavefront totals through LDS
+        __shared__ uint4 s_wt[NW / 4];
+        static_assert(NW % 4 == 0, "wavefront totals read four at a time");
+        const int wv = threadIdx.x / kWave;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kMyItems; ++k) mine += i_cy[k] & 0xffffu;
+        const uint32_t inc = wave_incl_scan(mine);
+        if (lane_id() == kWave - 1) reinterpret_cast<uint32_t *>(s_wt)[wv] = inc;
+        __syncthreads();
+        uint32_t run = S + inc - mine;
+#pragma unroll
+        for (int x4 = 0; x4 < NW / 4; ++x4) {
+            const uint4 t = s_wt[x4];
+            run += (4 * x4 < wv ? t.x : 0u) + (4 * x4 + 1 < wv ? t.y : 0u) +
+                   (4 * x4 + 2 < wv ? t.z : 0u) + (4 * x4 + 3 < wv ? t.w : 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < kMyItems; ++k) {
+            i_off[k] = run;
+            run += i_cy[k] & 0xffffu;
+            const int64_t j = b.j0 + (int64_t)threadIdx.x * kMyItems + k;
+            if (j < b.j1) ws.offsets[j] = i_off[k];
         }
     }
 

@@ -74,6 +74,8 @@ struct Ws {
     uint32_t *vhist;       // item sort (within each view): digit totals [view][kMaxPasses][kRadix]
     uint32_t *bin_cnt;     // tile lists by counting: [view][partition][local tile] pair counts,
                            // then their exclusive scan down each column
+    uint32_t *bin_ptot;    // tile lists by counting: pairs of each [view][partition]
+    uint32_t *bin_pstart;  // tile lists by counting: first pair slot of each [view][partition]
     uint32_t *pctr;        // radix sort: partition counters [kMaxPasses]
     uint64_t *lookback[2]; // radix sort: per (partition, digit) aggregate / prefix words
     uint32_t *ranges;
