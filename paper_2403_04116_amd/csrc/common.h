@@ -306,6 +306,47 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds, u
     return res;
 }
 
+// Resets the header words of a new frame other than the depth range.
+__device__ __forceinline__ void frame_header_reset(WsHeader *h) {
+    h->status = XG_OK;
+    h->n_pairs = 0;
+    h->item_sel = 0;
+    h->item_passes = 0;
+    h->queue_fwd = 0;
+    h->queue_bwd = 0;
+    h->done_fwd = 0;
+    h->done_bwd = 0;
+}
+
+// Folds this workgroup's share of the preprocess's per-block depth partials
+// ((min, max) pairs) into the header's depth range, which the preprocess
+// set to (0xffffffff, 0).  Called by every thread of the workgroup
+// (contains a barrier; at most 1024 threads).
+__device__ __forceinline__ void depth_range_fold(WsHeader *h, const uint32_t *part, int64_t nparts) {
+    uint32_t dmin = 0xffffffffu, dmax = 0u;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nparts;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        dmin = min(dmin, part[2 * k]);
+        dmax = max(dmax, part[2 * k + 1]);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, kWave));
+        dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, kWave));
+    }
+    __shared__ uint32_t smin[16], smax[16];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { smin[w] = dmin; smax[w] = dmax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) {
+            dmin = min(dmin, smin[k]);
+            dmax = max(dmax, smax[k]);
+        }
+        if (dmin != 0xffffffffu) atomicMin(&h->depth_min, dmin);
+        if (dmax != 0u) atomicMax(&h->depth_max, dmax);
+    }
+}
+
 // View index of a global tile id: the last view whose tile_offset <= tile.
 __device__ __forceinline__ int view_of_tile(const xg_camera *cams, int n_views, int tile) {
     int lo = 0, hi = n_views - 1;

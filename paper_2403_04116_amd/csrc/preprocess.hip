@@ -191,6 +191,12 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
                                                             const xg_camera *cams, Params p,
                                                             uint32_t *depth_part) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the frame's depth range starts empty; the item sort's first launch
+    // folds the per-block partials written below into it
+    if (idx == 0) {
+        ws.hdr->depth_min = 0xffffffffu;
+        ws.hdr->depth_max = 0u;
+    }
     // The workgroup's records (and 2-D gradient accumulators) form one
     // contiguous range; they are staged in LDS (16-byte part k of record t
     // at s_rec[k][t]: conflict-free) and written with whole cache lines.
@@ -285,37 +291,14 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
     }
 }
 
-// Resets the header for a new frame and reduces the per-block depth
-// partials into it (one block; nparts may be 0).
-__global__ __launch_bounds__(1024) void k_depth_range(WsHeader *h, const uint32_t *part, int nparts) {
-    uint32_t dmin = 0xffffffffu, dmax = 0u;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
-        dmin = min(dmin, part[2 * k]);
-        dmax = max(dmax, part[2 * k + 1]);
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, kWave));
-        dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, kWave));
-    }
-    __shared__ uint32_t smin[16], smax[16];
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) { smin[w] = dmin; smax[w] = dmax; }
-    __syncthreads();
+// Resets the header of a frame with no items (one thread).  With items,
+// the preprocess opens the depth range and the item sort's first launch
+// resets the rest and folds the depth partials into the range.
+__global__ void k_header_reset(WsHeader *h) {
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) {
-            dmin = min(dmin, smin[k]);
-            dmax = max(dmax, smax[k]);
-        }
-        h->depth_min = dmin;
-        h->depth_max = dmax;
-        h->status = XG_OK;
-        h->n_pairs = 0;
-        h->item_sel = 0;
-        h->item_passes = 0;
-        h->queue_fwd = 0;
-        h->queue_bwd = 0;
-        h->done_fwd = 0;
-        h->done_bwd = 0;
+        frame_header_reset(h);
+        h->depth_min = 0xffffffffu;
+        h->depth_max = 0u;
     }
 }
 
@@ -560,13 +543,15 @@ hipError_t launch_preprocess(const Ws &ws, const xg_gaussians &g, const xg_camer
                              const Params &p, hipStream_t s) {
     const int64_t nb = (ws.n_items + kPreThreads - 1) / kPreThreads;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    // depth partials live in the scan scratch; the count scan runs after
-    // k_depth_range has consumed them
+    // depth partials live in the scan scratch: the item sort's first launch
+    // reduces them into the header (and resets it for the frame) before
+    // anything else uses that scratch
     uint32_t *part = ws.scan_tmp;
     if (nb > 0)
         hipLaunchKernelGGL(k_preprocess, dim3((unsigned)nb), dim3(kPreThreads), 0, s, ws, g, cams, p,
                            part);
-    hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1024), 0, s, ws.hdr, part, (int)nb);
+    else
+        hipLaunchKernelGGL(k_header_reset, dim3(1), dim3(64), 0, s, ws.hdr);
     return hipGetLastError();
 }
 

@@ -201,9 +201,16 @@ __device__ __forceinline__ uint32_t *digit_bin(const Ws &ws, int64_t segment, in
 }
 
 // Zeroes the digit histograms, partition counters and the first pass's
-// look-back words of one sort.
+// look-back words of one sort.  The item sort's (depth_part set) also
+// resets the frame header (workgroup 0) and folds the preprocess's depth
+// partials into the depth range (every workgroup a share, atomically):
+// nothing here depends on those words.
 template <class S>
-__global__ __launch_bounds__(256) void k_sort_prep(Ws ws) {
+__global__ __launch_bounds__(256) void k_sort_prep(Ws ws, const uint32_t *depth_part, int64_t nparts) {
+    if (depth_part != nullptr) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) frame_header_reset(ws.hdr);
+        depth_range_fold(ws.hdr, depth_part, nparts);
+    }
     const Ctl c = S::ctl(ws);
     const int64_t parts = Parts<S>(ws, c).parts;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -592,11 +599,12 @@ __global__ __launch_bounds__(256) void k_pair_keys(Ws ws, const xg_camera *cams,
 }
 
 template <class S>
-hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s) {
+hipError_t radix_passes(const Ws &ws, int passes, int blocks, hipStream_t s,
+                        const uint32_t *depth_part = nullptr, int64_t nparts = 0) {
     const unsigned nb = (unsigned)(blocks > 0 ? blocks : 1);
     unsigned np = (unsigned)(((int64_t)blocks * kRadix + 255) / 256);
     if (np > 2048) np = 2048;
-    hipLaunchKernelGGL(k_sort_prep<S>, dim3(np > 0 ? np : 1), dim3(256), 0, s, ws);
+    hipLaunchKernelGGL(k_sort_prep<S>, dim3(np > 0 ? np : 1), dim3(256), 0, s, ws, depth_part, nparts);
     // segmented sorts: one histogram workgroup per partition
     const unsigned nh = S::kSegmented ? nb : (nb < 256 ? nb : 256);
     hipLaunchKernelGGL(k_sort_hist<S>, dim3(nh), dim3(S::kThreads), 0, s, ws, passes);
@@ -614,7 +622,9 @@ hipError_t launch_sort_items(const Ws &ws, hipStream_t s) {
     // bits, passes past the varying bits return at once
     const int passes = (32 + kRadixBits - 1) / kRadixBits;
     if (passes > kMaxPasses) return hipErrorInvalidValue;
-    return radix_passes<ItemSort>(ws, passes, ws.item_blocks, s);
+    // the preprocess left one depth (min, max) pair per workgroup in scan_tmp
+    const int64_t nparts = (ws.n_items + kPreThreads - 1) / kPreThreads;
+    return radix_passes<ItemSort>(ws, passes, ws.item_blocks, s, ws.scan_tmp, nparts);
 }
 
 
