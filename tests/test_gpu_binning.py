@@ -7,8 +7,11 @@ the oracle's sorted (tile << 32 | depth, index) pairs and tile ranges:
   rectangle is read from the record), views of uneven size;
 - emission + radix sort of the pairs by tile (a view with more tiles).
 
-Sampled pixels of each run are also checked against the brute-force
-renderer."""
+The item offsets the workspace exposes (the scan of the tile counts in
+depth order, written by the list scatter on the counting path and by the
+count scan on the other) are checked against a scan over the oracle's
+depth order.  Sampled pixels of each run are also checked against the
+brute-force renderer."""
 import math
 
 import numpy as np
@@ -19,6 +22,26 @@ import scenes as S
 from _gpu import compare_pixels, gpu_run, note, oracle_cams
 
 pytestmark = pytest.mark.gpu
+
+
+def _expected_offsets(g, cams, st):
+    """Item offsets: per view, the items in (depth bits, index) order, the
+    exclusive scan of their tile counts, from the pairs of the views before.
+    A culled item sorts as the largest kept depth of the frame (its key is
+    clamped there), by index among equal keys; its count is 0."""
+    proj = [O.project(g, c, st) for c in cams]
+    dmax = max(int(p["depth_bits"][p["kept"]].max()) for p in proj if p["kept"].any())
+    out, start = [], 0
+    for p in proj:
+        T = st.tile
+        r = p["rect"].astype(np.int64)
+        cnt = np.where(p["kept"], (r[:, 1] // T - r[:, 0] // T + 1) * (r[:, 3] // T - r[:, 2] // T + 1), 0)
+        key = np.where(p["kept"], p["depth_bits"].astype(np.int64), dmax)
+        order = np.argsort(key, kind="stable")
+        c_sorted = cnt[order]
+        out.append(start + np.concatenate([[0], np.cumsum(c_sorted)[:-1]]))
+        start += int(c_sorted.sum())
+    return np.concatenate(out).astype(np.int64), start
 
 
 def _check(g, angles, sizes, tile, label, sample=16):
@@ -33,6 +56,15 @@ def _check(g, angles, sizes, tile, label, sample=16):
     np.testing.assert_array_equal(gpu["keys"], pr["keys"])
     np.testing.assert_array_equal(gpu["values"], pr["values"])
     np.testing.assert_array_equal(gpu["ranges"], pr["ranges"])
+    # the item offsets the workspace exposes (scan of the tile counts in
+    # depth order), whichever path wrote them
+    import torch
+    fr = gpu["frame"]
+    n_items = int(g["means"].shape[0]) * len(cams)
+    offs = fr.ws_tensor(fr.layout.offsets, torch.int32, n_items).cpu().numpy().view(np.uint32)
+    exp, total = _expected_offsets(g, cams, st)
+    assert total == pr["keys"].size == fr.n_pairs()
+    np.testing.assert_array_equal(offs.astype(np.int64), exp)
     rng = np.random.default_rng(17)
     off = 0
     for v, c in enumerate(cams):
