@@ -472,54 +472,21 @@ constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRowRor8 = 0x128;   // row_ror:8
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 
-// Wavefront sums of the 7 gradient terms of G list entries (acc[e][q]),
+// Wavefront sums of the 7 gradient terms of 2 list entries (acc[e][q]),
 // halving the live values at every step (reduce-scatter).  The steps over
 // lane bits 5 and 4 swap wavefront halves and rows (gfx950 permlane swaps:
 // one swap and one add per pair of values), the lower bits read a partner
 // lane through DPP (two selects and one add per pair).  All VALU, no LDS
-// traffic.  Afterwards the lane map of RedLanes<G> tells which lanes hold
-// which total; a value without a partner at some step is summed in both
-// halves and its upper copy is dropped.
-//   G = 1: 19 instructions, lane 8q holds value q (q < 7);
-//   G = 2: 33 instructions, lane 32e + 4q holds value q of entry e;
-//   G = 4: 62 instructions, lane 16e + 2q holds value q of entry e.
+// traffic: 33 instructions (one entry alone takes 19).  Afterwards lane
+// 32 e + 4 q holds value q of entry e (q < 7); a value without a partner at
+// some step is summed in both halves and its upper copy is dropped.
 template <int G>
 struct RedLanes {
-    static_assert(G == 1 || G == 2 || G == 4, "groups of 1, 2 or 4 entries");
-    static constexpr int kEShift = G == 4 ? 4 : 5;   // entry = lane >> kEShift (G > 1)
-    static constexpr int kQShift = G == 4 ? 1 : (G == 2 ? 2 : 3);
-    __device__ static int entry(int lane) { return G == 1 ? 0 : lane >> kEShift; }
-    __device__ static int word(int lane) { return (lane >> kQShift) & 7; }
-    __device__ static bool adds(int lane) {
-        return (lane & ((1 << kQShift) - 1)) == 0 && word(lane) < 7;
-    }
+    static_assert(G == 2, "groups of 2 entries");
+    __device__ static int entry(int lane) { return lane >> 5; }
+    __device__ static int word(int lane) { return (lane >> 2) & 7; }
+    __device__ static bool adds(int lane) { return (lane & 3) == 0 && word(lane) < 7; }
 };
-
-__device__ __forceinline__ float wave_reduce_group(const float (&acc)[1][7]) {
-    const int lane = lane_id();
-    float v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        // lanes 0-31 keep value k, lanes 32-63 value k + 4 (value 3 twice)
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[0][k]),
-                                                        __float_as_uint(acc[0][k < 3 ? k + 4 : 3]),
-                                                        false, false);
-        v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        // even rows keep v[k], odd rows v[k + 2]
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 2]),
-                                                        false, false);
-        v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-    const bool h3 = lane & 8;
-    float x = (h3 ? v[1] : v[0]) + XG_DPP(h3 ? v[0] : v[1], kDppRowRor8);
-    x += XG_DPP(x, kDppQuadXor1);
-    x += XG_DPP(x, kDppQuadXor2);
-    x += XG_DPP(x, kDppHalfMirror);
-    return x;
-}
 
 __device__ __forceinline__ float wave_reduce_group(const float (&acc)[2][7]) {
     const int lane = lane_id();
@@ -546,42 +513,6 @@ __device__ __forceinline__ float wave_reduce_group(const float (&acc)[2][7]) {
         d[j] = (h3 ? c[j + 2] : c[j]) + XG_DPP(h3 ? c[j] : c[j + 2], kDppRowRor8);
     float x = (h2 ? d[1] : d[0]) + XG_DPP(h2 ? d[0] : d[1], kDppHalfMirror);
     x += XG_DPP(x, kDppQuadXor2);
-    x += XG_DPP(x, kDppQuadXor1);
-    return x;
-}
-
-__device__ __forceinline__ float wave_reduce_group(const float (&acc)[4][7]) {
-    const int lane = lane_id();
-    float b[14];
-#pragma unroll
-    for (int i = 0; i < 14; ++i) {
-        // flat index f = 7e + q: lanes 0-31 keep f = i, lanes 32-63 f = i + 14
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[i / 7][i % 7]),
-                                                        __float_as_uint(acc[(i + 14) / 7][(i + 14) % 7]),
-                                                        false, false);
-        b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-    float c[7];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        // even rows keep f = i, odd rows f = i + 7: c[q] is value q of entry lane >> 4
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[i]), __float_as_uint(b[i + 7]),
-                                                        false, false);
-        c[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-    // lane bit 3 selects q = i or i + 4 (q = 3 twice)
-    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2;
-    float d[4];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        d[i] = (h3 ? c[i + 4] : c[i]) + XG_DPP(h3 ? c[i] : c[i + 4], kDppRowRor8);
-    d[3] = c[3] + XG_DPP(c[3], kDppRowRor8);
-    // lane bit 2 selects d[j] or d[j + 2] (the mirror partner has bit 2 flipped)
-    float e[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-        e[j] = (h2 ? d[j + 2] : d[j]) + XG_DPP(h2 ? d[j] : d[j + 2], kDppHalfMirror);
-    float x = (h1 ? e[1] : e[0]) + XG_DPP(h1 ? e[0] : e[1], kDppQuadXor2);
     x += XG_DPP(x, kDppQuadXor1);
     return x;
 }
