@@ -120,7 +120,8 @@ typedef struct {
 typedef struct {
     size_t status;      /* int32: XG_OK or XG_ECAPACITY                       */
     size_t n_pairs;     /* int32: pairs emitted (may exceed the capacity)     */
-    size_t depth_range; /* uint32[2]: min and max depth bits of kept Gaussians */
+    size_t depth_range; /* uint32[2]: min, max depth bits of kept Gaussians */
+                        /* (set by xg_bin_sort)                               */
     size_t records;     /* 64-byte render records per (view, Gaussian)        */
     size_t counts;      /* uint32[n_views*n]: tiles touched (0 = culled)      */
     size_t offsets;     /* uint32[n_views*n]: scan of counts in depth order   */
@@ -176,8 +177,11 @@ xg_status xg_workspace_size(const xg_frame *f /* [host] */, size_t *bytes /* [ho
  * depth, culling, 2-D covariance Sigma'' = J W Sigma W^T J^T (rows/cols 1-2)
  * plus lowpass*I, its inverse in factored form, image-space centre, the
  * integer bounding rectangle of the alpha >= alpha_min footprint and the
- * number of tiles it touches.  Also resets the status word and clears the
- * per-view 2-D gradient accumulators used by xg_render_bwd. */
+ * number of tiles it touches.  Also clears the per-view 2-D gradient
+ * accumulators used by xg_render_bwd, and leaves the depth bounds of its
+ * workgroups for xg_bin_sort, whose first launch resets the status word
+ * and sets the frame's depth range (with no items, this call resets
+ * them). */
 xg_status xg_preprocess(const xg_frame *f /* [host] */, const xg_gaussians *g /* [host] */,
                         void *stream);
 
