@@ -242,7 +242,8 @@ xg_status xg_render_bwd(const xg_frame *f /* [host] */, const xg_gaussians *g /*
  * pixel's list backwards from n_contrib, recovering the transmittance by
  * division instead of reading stored per-contributor values, and
  * accumulates per (view, Gaussian) the 2-D gradients (image-space centre,
- * inverse 2-D covariance moments, opacity, intensity) in the workspace,
+ * inverse 2-D covariance moments, opacity times the opacity gradient,
+ * intensity) in the workspace,
  * reduced across each wavefront before one atomic add per (Gaussian,
  * wavefront).  Reads the per-entry block masks the forward left in the
  * workspace: final_t and n_contrib must come from xg_render_fwd,

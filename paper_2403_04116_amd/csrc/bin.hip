@@ -198,10 +198,11 @@ __global__ __launch_bounds__(kStartThreads) void k_bin_starts(Ws ws, const xg_ca
         before += s_sum[0][w];
         all += s_sum[1][w];
     }
-    const bool ok = ws.hdr->status == XG_OK && all <= (uint64_t)ws.cap;
+    const bool st_ok = ws.hdr->status == XG_OK;   // an item sort that gave up keeps its XG_EHIP
+    const bool ok = st_ok && all <= (uint64_t)ws.cap;
     if (v == 0 && threadIdx.x == 0) {
         ws.hdr->n_pairs = (int32_t)(all > 0x7fffffffull ? 0x7fffffffull : all);
-        if (all > (uint64_t)ws.cap) ws.hdr->status = XG_ECAPACITY;
+        if (st_ok && all > (uint64_t)ws.cap) ws.hdr->status = XG_ECAPACITY;
     }
     // partition starts (below the capacity whenever they are used)
     uint32_t carry = (uint32_t)before;

@@ -387,14 +387,16 @@ __global__ __launch_bounds__(256) void k_emit(Ws ws, const xg_camera *cams, int 
 // Adjoint of the projection for one Gaussian, summed over views.
 // grad2d per (view, Gaussian) holds pixel sums of g_p = dL/dpower_p times
 // the offsets d = pixel centre - u:
-//   (sum g dx, sum g dy, sum g dx^2, sum g dx dy, sum g dy^2, dL/do, dL/di, 0)
+//   (sum g dx, sum g dy, sum g dx^2, sum g dx dy, sum g dy^2, sum g, dL/di, 0)
+// where sum g = o dL/do (alpha = o G before the clamp, which has no
+// derivative), so dL/do is that sum over all views divided by the opacity.
 // With power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 and [[A, B], [B, C]] the
 // inverse 2-D covariance: dL/du = [[A, B], [B, C]] (sum g d),
 // dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy, dL/dC = -sum g dy^2 / 2.
 // ACCUM: add into the gradients; else write them (zeros for a Gaussian no
 // view touched).
 template <bool ACCUM>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
+__global__ __launch_bounds__(256, 3) void k_preprocess_bwd(Ws ws, xg_gaussians g, const xg_camera *cams,
                                                         Params p, xg_grads gr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ws.n) return;
@@ -494,6 +496,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         for (int a = 0; a < 3; ++a) gm[a] += r[a] * gtx + r[3 + a] * gty + r[6 + a] * gtz;
     }
     if (ACCUM && !any) return;
+    // kept items have opacity >= alpha_min (single precision: the division
+    // adds no registers to this double-precision kernel)
+    const float gof = any ? (float)go / g.opacity[i] : 0.0f;
     float *om = gr.means + 3 * (int64_t)i;
     float *os = gr.scales + 3 * (int64_t)i;
     float *oq = gr.quats + 4 * (int64_t)i;
@@ -502,14 +507,14 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Ws ws, xg_gaussians g, c
         for (int a = 0; a < 3; ++a) { om[a] += (float)gm[a]; os[a] += (float)gs[a]; }
 #pragma unroll
         for (int a = 0; a < 4; ++a) oq[a] += (float)gq[a];
-        gr.opacity[i] += (float)go;
+        gr.opacity[i] += gof;
         gr.intensity[i] += (float)gi;
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) { om[a] = (float)gm[a]; os[a] = (float)gs[a]; }
 #pragma unroll
         for (int a = 0; a < 4; ++a) oq[a] = (float)gq[a];
-        gr.opacity[i] = (float)go;
+        gr.opacity[i] = gof;
         gr.intensity[i] = (float)gi;
     }
 }

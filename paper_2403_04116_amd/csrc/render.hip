@@ -652,12 +652,14 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                 const float gT = ge * Tj;
                 float *v = acc[e];
                 v[6] = gT * ev.alpha;                          // dL/d intensity
-                const float galpha = gT * (it - R);            // dL/d alpha
-                R = act ? fmaf(it, ev.alpha, om * R) : R;
+                const float dR = it - R;
+                const float galpha = gT * dR;                  // dL/d alpha
+                // R after this Gaussian: i alpha + (1 - alpha) R
+                R = fmaf(act ? ev.alpha : 0.0f, dR, R);
                 Tr = Tj;
                 const float ga = (ev.a > amax) ? 0.0f : galpha;
-                v[5] = ga * ev.G;                              // dL/d opacity
                 const float gp = ga * ev.a;                    // dL/d power, power = -d^T Q d / 2
+                v[5] = gp;                                     // opacity x dL/d opacity (a = o G)
                 // moments of gp over the pixel offsets d = pixel - u; the inverse
                 // covariance is applied once per (view, Gaussian)
                 v[0] = gp * ev.dx;
