@@ -635,8 +635,10 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             const bool act = inr && ev.alpha >= amin;
             if (__any(act)) {
                 // Every lane runs the same arithmetic; a lane that is not a
-                // contributor gets a zero upstream gradient (exact zeros in the
-                // reduction) and keeps its transmittance and R.
+                // contributor adds exact zeros to the reduction (its alpha
+                // taken as 0, its alpha gradient masked) and keeps its
+                // transmittance and R.
+                const float aact = act ? ev.alpha : 0.0f;
                 const float om = 1.0f - ev.alpha;
                 float Tj;   // T before this Gaussian
                 if (STORE) {
@@ -647,17 +649,18 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                 } else {
                     Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;
                 }
-                const float ge = act ? g : 0.0f;
                 const float it = sb.z;
-                const float gT = ge * Tj;
+                const float gT = g * Tj;
                 float *v = acc[e];
-                v[6] = gT * ev.alpha;                          // dL/d intensity
+                v[6] = gT * aact;                              // dL/d intensity
                 const float dR = it - R;
                 const float galpha = gT * dR;                  // dL/d alpha
                 // R after this Gaussian: i alpha + (1 - alpha) R
-                R = fmaf(act ? ev.alpha : 0.0f, dR, R);
+                R = fmaf(aact, dR, R);
                 Tr = Tj;
-                const float ga = (ev.a > amax) ? 0.0f : galpha;
+                // no alpha gradient through the clamp, nor for a lane that is
+                // not a contributor
+                const float ga = (act && ev.a <= amax) ? galpha : 0.0f;
                 const float gp = ga * ev.a;                    // dL/d power, power = -d^T Q d / 2
                 v[5] = gp;                                     // opacity x dL/d opacity (a = o G)
                 // moments of gp over the pixel offsets d = pixel - u; the inverse
