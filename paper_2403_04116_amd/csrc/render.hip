@@ -126,13 +126,14 @@ __device__ __forceinline__ uint32_t subblock_mask(int xl, int xh, int yl, int yh
 // smaller, and for a box holding the origin both lines give 0).  Along each
 // line E is a one-dimensional quadratic minimised at -rx Yn resp. -ry Xn
 // (rx = qb / qa, ry = qa qb / (qb^2 + qc^2)), clamped to the edge.
+// (X0 <= X1 and Y0 <= Y1, all finite: each clamp is one median of three)
 __device__ __forceinline__ float box_min_exponent(float qa, float qb, float qc, float rx, float ry,
                                                   float X0, float X1, float Y0, float Y1) {
-    const float xn = fminf(fmaxf(0.0f, X0), X1);
-    const float yn = fminf(fmaxf(0.0f, Y0), Y1);
-    const float x = fminf(fmaxf(-rx * yn, X0), X1);
+    const float xn = __builtin_amdgcn_fmed3f(0.0f, X0, X1);
+    const float yn = __builtin_amdgcn_fmed3f(0.0f, Y0, Y1);
+    const float x = __builtin_amdgcn_fmed3f(-rx * yn, X0, X1);
     const float e1 = qa * x + qb * yn, e2 = qc * yn;
-    const float y = fminf(fmaxf(-ry * xn, Y0), Y1);
+    const float y = __builtin_amdgcn_fmed3f(-ry * xn, Y0, Y1);
     const float f1 = qa * xn + qb * y, f2 = qc * y;
     return fminf(e1 * e1 + e2 * e2, f1 * f1 + f2 * f2);
 }
@@ -190,15 +191,24 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
             const float qa = ra.z, qb = ra.w, qc = rb.x;
             const float rx = qb * __builtin_amdgcn_rcpf(qa);
             const float ry = qa * qb * __builtin_amdgcn_rcpf(qb * qb + qc * qc);
-            // pixel centres relative to the Gaussian centre
+            // pixel centres relative to the Gaussian centre; the box edges
+            // clamp the rectangle's (offset once) to each sub-block's, which
+            // rounds the same as offsetting the clamped integer (a rounded
+            // sum is monotone in its operands)
             const float ox = (float)(tg.x0 - tg.rx) + 0.5f - ux;
             const float oy = (float)(tg.y0 - tg.ry) + 0.5f - uy;
+            const float rxl = ox + (float)xl, rxh = ox + (float)xh;
+            const float ryl = oy + (float)yl, ryh = oy + (float)yh;
 #pragma unroll
             for (int sb = 0; sb < SB * SB; ++sb) {
                 if (!((m >> sb) & 1u)) continue;
                 const int bx = (sb % SB) * 8, by = (sb / SB) * 8;
-                const float X0 = ox + (float)max(xl, bx), X1 = ox + (float)min(xh, bx + 7);
-                const float Y0 = oy + (float)max(yl, by), Y1 = oy + (float)min(yh, by + 7);
+                // the sub-block touches the rectangle, so its edges lie on the
+                // right sides of the rectangle's: each clamp is a median of three
+                const float X0 = __builtin_amdgcn_fmed3f(rxl, ox + (float)bx, rxh);
+                const float X1 = __builtin_amdgcn_fmed3f(rxl, ox + (float)(bx + 7), rxh);
+                const float Y0 = __builtin_amdgcn_fmed3f(ryl, oy + (float)by, ryh);
+                const float Y1 = __builtin_amdgcn_fmed3f(ryl, oy + (float)(by + 7), ryh);
                 if (box_min_exponent(qa, qb, qc, rx, ry, X0, X1, Y0, Y1) > thr) mc &= ~(1u << sb);
             }
             if (CULL) m = mc;
