@@ -31,12 +31,14 @@ static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
 // by every tile that lists the Gaussian: 64 bytes, one cache line, so a
 // staged list entry is a single aligned gather.
 //   a: (u_x - floor(u_x), u_y - floor(u_y), qa, qb)
-//   b: (qc, opacity, intensity, float bits of depth)
+//   b: (qc, -log2(opacity), intensity, float bits of depth)
 //   c: (floor(u_x), floor(u_y), x_lo | x_hi << 16, y_lo | y_hi << 16)
 //   d: unused
 // (qa, qb, qc) factor the inverse 2-D covariance scaled by k = log2(e)/2:
 //   k * d^T Sigma''^-1 d = (qa dx + qb dy)^2 + (qc dy)^2
-// so that exp(-d^T Sigma''^-1 d / 2) = exp2(-(that)).
+// so that exp(-d^T Sigma''^-1 d / 2) = exp2(-(that)), and the opacity times
+// it, the a of Eq. 10, is exp2(-(that - log2 opacity)): the blend kernels
+// evaluate one exponential and no product.
 struct alignas(64) Record {
     float4 a;
     float4 b;

@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(Ws ws, xg_gaussians 
             fy_ = fmin(fmax(fy_, -1073741824.0), 1073741824.0);
             uint32_t dbits = __float_as_uint(ko.tz);
             ra = make_float4((float)(ux - fx_), (float)(uy - fy_), (float)qa, (float)qb);
-            rb = make_float4((float)qc, o, g.intensity[i], __uint_as_float(dbits));
+            // -log2(o) (+inf for o = 0: then every a is 0)
+            rb = make_float4((float)qc, -log2f(o), g.intensity[i], __uint_as_float(dbits));
             const int4 ci = make_int4((int)fx_, (int)fy_, ko.xl | (ko.xh << 16), ko.yl | (ko.yh << 16));
             rc = make_float4(__int_as_float(ci.x), __int_as_float(ci.y), __int_as_float(ci.z),
                              __int_as_float(ci.w));

@@ -27,11 +27,13 @@ namespace xg {
 namespace {
 
 struct Eval {
-    float dx, dy, y1, y2, G, a, alpha;
+    float dx, dy, y1, y2, a, alpha;
 };
 
 // alpha of one staged Gaussian at a pixel centre (px, py), both relative
-// to the block reference point.  sa = (ux, uy, qa, qb), sb = (qc, o, intensity, rectangle word).
+// to the block reference point.  sa = (ux, uy, qa, qb), sb = (qc, -log2 o,
+// intensity, rectangle word): a = o G = exp2(-(E - log2 o)), with E the
+// scaled Mahalanobis term, so the opacity enters the exponent's sum.
 __device__ __forceinline__ Eval splat_eval(const float4 &sa, const float4 &sb, float px, float py,
                                            float amax) {
 #pragma clang fp contract(off)
@@ -40,9 +42,8 @@ __device__ __forceinline__ Eval splat_eval(const float4 &sa, const float4 &sb, f
     e.dy = py - sa.y;
     e.y1 = fmaf(sa.w, e.dy, sa.z * e.dx);
     e.y2 = sb.x * e.dy;
-    const float E = fmaf(e.y2, e.y2, e.y1 * e.y1);
-    e.G = __builtin_amdgcn_exp2f(-E);
-    e.a = sb.y * e.G;
+    const float E = fmaf(e.y2, e.y2, fmaf(e.y1, e.y1, sb.y));
+    e.a = __builtin_amdgcn_exp2f(-E);
     e.alpha = fminf(e.a, amax);
     return e;
 }
@@ -165,6 +166,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
     constexpr int SB = T / 8;
     static_assert(!(MASKIO && DUAL), "the counting forward neither stores nor loads masks");
     SubMask<T> *gmask = reinterpret_cast<SubMask<T> *>(ws.entry_mask);
+    const float lg_amin = -__builtin_amdgcn_logf(amin);   // log2(1 / alpha_min)
     for (int k = threadIdx.x; k < cnt; k += NT) {
         const uint32_t gi = vals[b0 + k] & ws.pair_gmask;   // Gaussian index (packed or not)
         const int64_t rid = (int64_t)tg.view * ws.n + gi;
@@ -184,7 +186,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
         if (MASKIO == 2) {
             m = gmask[b0 + k];
         } else if (CULL || DUAL) {
-            const float thr = __builtin_amdgcn_logf(rb.y * __builtin_amdgcn_rcpf(amin)) * 1.00001f + 1e-3f;
+            const float thr = (lg_amin - rb.y) * 1.00001f + 1e-3f;   // log2(o / alpha_min) + margin
             // the edge minimisers' slopes, with approximate reciprocals: an
             // argmin off by a rounding error raises the minimum by a
             // second-order amount, far inside the margin of thr
@@ -216,7 +218,7 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
             if (MASKIO == 1) gmask[b0 + k] = (SubMask<T>)m;
         }
         s_mask[k] = (uint16_t)m;
-        if (s_rid) s_rid[k] = (uint32_t)rid;
+        if (s_rid) s_rid[4 * k] = (uint32_t)rid;   // 16-byte slots, like the records
         if (s_c) s_c[k] = rec.d;   // RGB colour of the view (comparison model)
     }
 }
@@ -254,7 +256,7 @@ struct BlendLds {
     float4 a[B];
     float4 b[B];
     float4 c[CH == 3 ? B : 1];
-    uint32_t rid[B];
+    uint32_t rid[4 * B];   // record index of entry k at rid[4 k] (read at the entry's byte offset)
     uint16_t mask[B];
     uint16_t cmask[CNT ? B : 1];
     alignas(16) uint16_t list[NW][B];
@@ -571,6 +573,9 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         last = n_contrib[o];
         if (g == 0.0f) last = 0;
     }
+    // recomputed variant: dL/dI times the transmittance, divided back one
+    // contributor at a time (T before a Gaussian = T after it / (1 - alpha))
+    float gTr = g * Tr;
     // stored variant: index of the next contributor (counting down) and its
     // stored transmittance, loaded one contributor ahead of its use;
     // contributors past the stored slots divide the transmittance back
@@ -596,7 +601,9 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
     const int lane_e = RedLanes<G>::entry(lane);
     const int lane_q = RedLanes<G>::word(lane);
     const bool lane_adds = RedLanes<G>::adds(lane);
-    float *g2q = ws.grad2d + lane_q;
+    const uint32_t lane_q4 = 4u * (uint32_t)lane_q;
+    const bool small_rid = ws.n_items < (int64_t)1 << 27;   // 32 B x records below 4 GiB
+    const bool adds_lo = lane_adds && lane_e == 0, adds_hi = lane_adds && lane_e == 1;
     for (int end = bmax; end > 0; end -= B) {
         const int b0 = max(end - B, 0);
         const int cnt = end - b0;
@@ -627,7 +634,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
           // and are left out of the atomics (bit e of live4)
           float acc[G][7];
           uint32_t live4 = 0;
-          int rid = 0;   // Gaussian record of entry lane_e
+          uint32_t rid = 0;   // Gaussian record of entry lane_e
 #pragma unroll
           for (int u = 7; u >= 0; --u) {
             const int e = u & (G - 1);
@@ -649,25 +656,28 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                 // taken as 0, its alpha gradient masked) and keeps its
                 // transmittance and R.
                 const float aact = act ? ev.alpha : 0.0f;
-                const float om = 1.0f - ev.alpha;
-                float Tj;   // T before this Gaussian
+                float gT;   // dL/dI times T before this Gaussian
                 if (STORE) {
-                    Tj = act ? (c < ts.slots ? tnext : Tr * __builtin_amdgcn_rcpf(om)) : Tr;
+                    const float om = 1.0f - ev.alpha;
+                    const float Tj = act ? (c < ts.slots ? tnext : Tr * __builtin_amdgcn_rcpf(om)) : Tr;
                     const int cn = act ? c - 1 : c;
                     if (act && cn >= 0 && cn < ts.slots) tnext = tbase[(int64_t)cn * NT];
                     c = cn;
+                    Tr = Tj;
+                    gT = g * Tj;
                 } else {
-                    Tj = act ? Tr * __builtin_amdgcn_rcpf(om) : Tr;
+                    // a lane that is not a contributor divides by 1 - 0 (the
+                    // reciprocal of 1 is exact) and keeps its value
+                    gT = gTr * __builtin_amdgcn_rcpf(1.0f - aact);
+                    gTr = gT;
                 }
                 const float it = sb.z;
-                const float gT = g * Tj;
                 float *v = acc[e];
                 v[6] = gT * aact;                              // dL/d intensity
                 const float dR = it - R;
                 const float galpha = gT * dR;                  // dL/d alpha
                 // R after this Gaussian: i alpha + (1 - alpha) R
                 R = fmaf(aact, dR, R);
-                Tr = Tj;
                 // no alpha gradient through the clamp, nor for a lane that is
                 // not a contributor
                 const float ga = (act && ev.a <= amax) ? galpha : 0.0f;
@@ -680,7 +690,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                 v[2] = v[0] * ev.dx;
                 v[3] = v[0] * ev.dy;
                 v[4] = v[1] * ev.dy;
-                if (lane_e == e) rid = (int)s_rid[off >> 4];
+                if (lane_e == e) rid = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s_rid) + off);
                 live4 |= 1u << e;
             } else {
 #pragma unroll
@@ -688,7 +698,17 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
             }
             if (e == 0 && live4 != 0) {
                 const float x = wave_reduce_group(acc);
-                if (lane_adds && ((live4 >> lane_e) & 1u)) atomicAdd(g2q + 8 * (int64_t)rid, x);
+                // the adding lanes of the live entries (a wavefront-uniform
+                // choice per half: no per-lane test of live4)
+                const bool l0 = live4 & 1u, l1 = live4 & 2u;
+                if ((l0 && adds_lo) || (l1 && adds_hi)) {
+                    if (small_rid) {   // 32-bit byte offset from the array base
+                        atomicAdd(reinterpret_cast<float *>(reinterpret_cast<char *>(ws.grad2d) + (rid << 5 | lane_q4)), x);
+                    } else {
+                        atomicAdd(ws.grad2d + 8 * (int64_t)rid + lane_q, x);
+                        __asm__ volatile("" ::: "memory");   // keeps the two atomics apart
+                    }
+                }
                 live4 = 0;
             }
           }
