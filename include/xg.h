@@ -198,7 +198,11 @@ xg_status xg_preprocess(const xg_frame *f /* [host] */, const xg_gaussians *g /*
  * fills the per-tile [start, end) ranges and the pair count; more pairs
  * than the capacity raise XG_ECAPACITY (no pair is written, every range
  * is empty).  A sort whose partitions cannot complete reports XG_EHIP in
- * the status word. */
+ * the status word.  Last, the order in which the blend launches take the
+ * tiles: each XCD's contiguous block of tiles (workgroup b runs on XCD
+ * b % 8) from the longest list to the shortest, so no long tile starts
+ * near the end of a launch; the render calls read it (any order gives the
+ * same results). */
 xg_status xg_bin_sort(const xg_frame *f /* [host] */, void *stream);
 
 /* Stage 3 (Eq. 10): front-to-back blending of every pixel over its tile's
@@ -331,6 +335,7 @@ typedef struct {
     const float *grad2d;
     int32_t pair_index_bits;
     int64_t total_tiles, total_pixels;
+    const int32_t *tile_order;   /* int32[total_tiles], written by xg_bin_sort */
 } xg_ws_view;
 xg_status xg_ws_inspect(const xg_frame *f /* [host] */, xg_ws_view *out /* [host] */);
 

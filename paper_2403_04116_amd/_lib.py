@@ -88,7 +88,7 @@ class XgWsView(C.Structure):
     _fields_ = [("status", C.c_void_p), ("n_pairs", C.c_void_p), ("pair_tiles", C.c_void_p),
                 ("pair_values", C.c_void_p), ("ranges", C.c_void_p), ("records", C.c_void_p),
                 ("grad2d", C.c_void_p), ("pair_index_bits", C.c_int32), ("total_tiles", C.c_int64),
-                ("total_pixels", C.c_int64)]
+                ("total_pixels", C.c_int64), ("tile_order", C.c_void_p)]
 
 
 if not os.path.exists(LIB_PATH):

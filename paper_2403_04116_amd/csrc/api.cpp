@@ -71,7 +71,7 @@ xg_status check_frame(const xg_frame *f, bool need_ws, int64_t *tot_px, int64_t 
 struct Plan {
     xg_ws_layout lay;
     size_t icounts, scan_tmp, ikeys[2], ivals[2], ptile[2], pval[2], ghist, vhist, bin_cnt, bin_ptot,
-        bin_pstart, lookback[2], tile_order, ssim, entry_mask;
+        bin_pstart, lookback[2], tile_order, xcd_order, ssim, entry_mask;
     int64_t total_px, total_tiles, n_items;
     int32_t item_blocks, pair_blocks, tile_bits, pair_passes, pair_gbits, bin_tiles, bin_ppv;
 };
@@ -134,6 +134,7 @@ xg_status make_plan(const xg_frame *f, bool need_ws, Plan &P) {
     P.entry_mask = o;         o = align_up(o + (f->settings.tile > 16 ? 2 : 1) * (size_t)cap);
     L.grad2d = o;             o = align_up(o + 32 * (size_t)ni);
     P.tile_order = o;         o = align_up(o + 4 * (size_t)P.total_tiles);
+    P.xcd_order = o;          o = align_up(o + 4 * (size_t)P.total_tiles);
     P.ssim = o;               o = align_up(o + 12 * (size_t)P.total_px + 4 * (size_t)loss_tiles(f->cams, f->n_views));
     L.pair_tiles = P.ptile[P.pair_passes & 1];
     L.pair_values = P.pair_gbits ? P.ptile[P.pair_passes & 1] : P.pval[P.pair_passes & 1];
@@ -172,6 +173,7 @@ Ws resolve(const xg_frame *f, const Plan &P) {
     w.entry_mask = b + P.entry_mask;
     w.grad2d = (float *)(b + P.lay.grad2d);
     w.tile_order = (int32_t *)(b + P.tile_order);
+    w.xcd_order = (int32_t *)(b + P.xcd_order);
     w.ssim = (float *)(b + P.ssim);
     w.cap = f->pair_capacity;
     w.n_items = P.n_items;
@@ -345,6 +347,8 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
     } else {
         e = launch_ranges(ws, false, s);
     }
+    // the blend launches' tile order, from the ranges just built
+    if (e == hipSuccess) e = launch_xcd_order(ws, s);
     return hip_status(e);
 }
 
@@ -564,6 +568,7 @@ xg_status xg_ws_inspect(const xg_frame *f, xg_ws_view *out) {
     out->pair_index_bits = (int32_t)P.lay.pair_index_bits;
     out->total_tiles = P.total_tiles;
     out->total_pixels = P.total_px;
+    out->tile_order = (const int32_t *)(b + P.xcd_order);
     return XG_OK;
 }
 

@@ -60,6 +60,18 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return x * q + min(x, r) + i;
 }
 
+// Tile of workgroup b of a one-workgroup-per-tile launch over n tiles: XCD
+// b % kXcds walks its contiguous block of tiles in the order the list
+// builder left in `order` (longest list first, so the longest tiles start
+// early and none is left to run alone at the end of the launch).  An entry
+// outside [0, n) (a workspace whose lists were never built) falls back to
+// the block's natural order instead of reading out of bounds.
+__device__ __forceinline__ int ordered_tile(const int32_t *order, int b, int n) {
+    const int i = xcd_tile(b, n);
+    const int t = order[i];
+    return (unsigned)t < (unsigned)n ? t : i;
+}
+
 // Device view of a workspace, resolved on the host from the layout.
 struct Ws {
     WsHeader *hdr;
@@ -87,6 +99,7 @@ struct Ws {
     float *ssim;           // loss: three per-pixel SSIM partial-derivative maps, then one
                            // loss share per 48 x 8 loss strip
     int32_t *tile_order;   // persistent queue: tiles in work order
+    int32_t *xcd_order;    // one-workgroup-per-tile launches: each XCD's block of tiles, longest list first
     int64_t cap;
     int64_t n_items;       // n_views * n
     int64_t total_tiles;
@@ -217,6 +230,7 @@ hipError_t launch_emit(const Ws &ws, const xg_camera *cams, const Params &p, hip
 hipError_t launch_sort_pairs(const Ws &ws, hipStream_t s);
 hipError_t launch_ranges(const Ws &ws, bool cleared, hipStream_t s);  // cleared: by the pair sort
 hipError_t launch_tile_order(const Ws &ws, hipStream_t s);
+hipError_t launch_xcd_order(const Ws &ws, hipStream_t s);
 hipError_t launch_bin_lists(const Ws &ws, const xg_camera *cams, const Params &p, hipStream_t s);
 hipError_t launch_pair_keys(const Ws &ws, const xg_camera *cams, uint64_t *keys, uint32_t *vals,
                             int64_t cap, hipStream_t s);

@@ -449,7 +449,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(Ws ws, const xg_camera *ca
                                                       TStore ts, L1Fuse l1) {
     __shared__ BlendLds<T, B, 1, COUNT> sh;
     if (!PERSIST) {
-        fwd_tile<T, B, COUNT, STORE>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
+        fwd_tile<T, B, COUNT, STORE>(ordered_tile(ws.xcd_order, blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
                                      final_t, n_contrib, counts, ts, l1, sh);
         return;
     }
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd_rgb(Ws ws, const xg_camera
                                                           float *image, float *final_t,
                                                           int32_t *n_contrib) {
     __shared__ BlendLds<T, B, 3> sh;
-    fwd_tile<T, B, false, false, 3>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
+    fwd_tile<T, B, false, false, 3>(ordered_tile(ws.xcd_order, blockIdx.x, (int)ws.total_tiles), ws, cams, p, image,
                                     final_t, n_contrib, nullptr, TStore{nullptr, nullptr, 0},
                                     L1Fuse{nullptr, nullptr, 0.0f}, sh);
 }
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(Ws ws, const xg_camera *ca
                                                       const int32_t *n_contrib, TStore ts) {
     __shared__ BlendLds<T, B> sh;
     if (!PERSIST) {
-        bwd_tile<T, B, STORE>(xcd_tile(blockIdx.x, (int)ws.total_tiles), ws, cams, p, dl_dimage,
+        bwd_tile<T, B, STORE>(ordered_tile(ws.xcd_order, blockIdx.x, (int)ws.total_tiles), ws, cams, p, dl_dimage,
                               final_t, n_contrib, ts, sh);
         return;
     }

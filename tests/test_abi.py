@@ -353,6 +353,12 @@ def test_ws_inspect_matches_layout():
     assert v.ranges == base + lay.ranges and v.records == base + lay.records
     assert v.grad2d == base + lay.grad2d and v.pair_index_bits == lay.pair_index_bits
     assert v.total_tiles == 16 + 3 * 2 and v.total_pixels == 64 * 64 + 40 * 24
+    # the blend launches' tile order: int32 per tile, inside the workspace,
+    # clear of the public sub-buffers
+    assert base <= v.tile_order and v.tile_order + 4 * v.total_tiles <= base + lay.total
+    for off in (lay.status, lay.records, lay.counts, lay.offsets, lay.pair_tiles, lay.pair_values,
+                lay.ranges, lay.grad2d):
+        assert v.tile_order != base + off
     f.ws = 0
     with pytest.raises(X.XgError):
         X.xg_ws_inspect(f)

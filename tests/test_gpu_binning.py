@@ -44,6 +44,29 @@ def _expected_offsets(g, cams, st):
     return np.concatenate(out).astype(np.int64), start
 
 
+def _check_tile_order(fr, ranges):
+    """The blend launches' tile order (written by the list builder): workgroup
+    b runs on XCD b % 8, which takes the b-th block of a split of the tiles
+    into 8 contiguous blocks (sizes differing by at most one); within its
+    block the order is a permutation of the block, longest list first in
+    buckets of an eighth of an octave (a float32 log2 on the GPU, so a
+    length may cross into the neighbouring bucket)."""
+    import torch
+    import paper_2403_04116_amd as P
+    n = int(fr.total_tiles)
+    v = P.xg_ws_inspect(fr.frame)
+    order = fr.ws_tensor(v.tile_order - fr.ws.data_ptr(), torch.int32, n).cpu().numpy().astype(np.int64)
+    r = np.asarray(ranges, dtype=np.int64).reshape(-1, 2)
+    q, rem = divmod(n, 8)
+    for x in range(8):
+        t0 = x * q + min(x, rem)
+        t1 = t0 + q + (1 if x < rem else 0)
+        blk = order[t0:t1]
+        np.testing.assert_array_equal(np.sort(blk), np.arange(t0, t1))
+        f = 8.0 * np.log2((r[blk, 1] - r[blk, 0]).astype(np.float64) + 1.0)
+        assert np.all(np.diff(f) < 1.0 + 1e-3), f"XCD block {x}: tiles not longest first"
+
+
 def _check(g, angles, sizes, tile, label, sample=16):
     note(f"binning {label}: GPU")
     gpu = gpu_run(g, angles, sizes, tile=tile, backward=False)
@@ -65,6 +88,7 @@ def _check(g, angles, sizes, tile, label, sample=16):
     exp, total = _expected_offsets(g, cams, st)
     assert total == pr["keys"].size == fr.n_pairs()
     np.testing.assert_array_equal(offs.astype(np.int64), exp)
+    _check_tile_order(fr, pr["ranges"])
     rng = np.random.default_rng(17)
     off = 0
     for v, c in enumerate(cams):
