@@ -760,7 +760,11 @@ def main():
                      "traffic": traffic, "launch_ms": dom_ms, "lane_ops_per_launch": dom_ops,
                      "work_model": f"fwd {LANE_OPS_EVAL_FWD}/evaluation; bwd {LANE_OPS_EVAL_BWD}/"
                                    f"revisited evaluation + {WAVE_INSTR_REDUCTION} x {WAVE} per "
-                                   "(Gaussian, wavefront) reduction"},
+                                   "(Gaussian, wavefront) reduction",
+                     "note": "the model prices each reduction as a 6-level butterfly per value "
+                             f"({WAVE_INSTR_REDUCTION} wavefront instructions); the backward's "
+                             "reduce-scatter issues about 18 per entry, so the model's lane "
+                             "operations exceed the instructions issued and frac can pass 1"},
         "cpu_baseline": cpu,
         "graph": graph,
         "eager": eager,
