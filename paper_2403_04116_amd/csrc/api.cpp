@@ -343,12 +343,14 @@ xg_status xg_bin_sort(const xg_frame *f, void *stream) {
             if (e == hipSuccess) e = launch_emit(ws, f->cams_dev, p, s);
             if (e == hipSuccess) e = launch_sort_pairs(ws, s);
             if (e == hipSuccess) e = launch_ranges(ws, true, s);
+            // the blend launches' tile order (the counting path's list
+            // scatter writes it)
+            if (e == hipSuccess) e = launch_xcd_order(ws, s);
         }
     } else {
         e = launch_ranges(ws, false, s);
+        if (e == hipSuccess) e = launch_xcd_order(ws, s);
     }
-    // the blend launches' tile order, from the ranges just built
-    if (e == hipSuccess) e = launch_xcd_order(ws, s);
     return hip_status(e);
 }
 

@@ -37,10 +37,10 @@ struct BinPart {
     int tiles_x, tiles, toff;
 };
 
-__device__ __forceinline__ BinPart bin_part(const Ws &ws, const xg_camera *cams, int tile) {
+__device__ __forceinline__ BinPart bin_part(const Ws &ws, const xg_camera *cams, int tile, int part) {
     BinPart b;
-    b.view = blockIdx.x / ws.bin_ppv;
-    b.q = blockIdx.x - b.view * ws.bin_ppv;
+    b.view = part / ws.bin_ppv;
+    b.q = part - b.view * ws.bin_ppv;
     const int64_t vbase = (int64_t)b.view * ws.n;
     b.j0 = vbase + (int64_t)b.q * kBinItems;
     b.j1 = min(b.j0 + kBinItems, vbase + ws.n);
@@ -56,7 +56,7 @@ static_assert(kBinItems % kCountThreads == 0, "whole items per thread");
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(Ws ws, const xg_camera *cams, int tile) {
     __shared__ uint32_t cnt[kBinMaxTiles];
-    const BinPart b = bin_part(ws, cams, tile);
+    const BinPart b = bin_part(ws, cams, tile, blockIdx.x);
     for (int t = threadIdx.x; t < b.tiles; t += kCountThreads) cnt[t] = 0;
     __syncthreads();
     const int sel = ws.hdr->item_sel & 1;
@@ -267,15 +267,23 @@ __global__ __launch_bounds__(NW * kWave, NW == 16 ? 8 : 2) void k_bin_scatter(Ws
     constexpr int kHashBits = 6, kHash = 1 << kHashBits;
     __shared__ uint64_t s_tab[NW][kHash];
 
+    // the first kXcds workgroups write the blend launches' tile order (the
+    // ranges are final; every status, since the blends read it even when
+    // the lists are empty), in slots the partitions leave idle
+    if ((int)blockIdx.x < kXcds) {
+        xcd_order_block(ws, blockIdx.x, base, s_lst);
+        return;
+    }
+    const int part = (int)blockIdx.x - kXcds;
     if (ws.hdr->status != XG_OK) return;
-    const BinPart b = bin_part(ws, cams, tile);
+    const BinPart b = bin_part(ws, cams, tile, part);
     if (b.j0 >= b.j1) return;
     // the partition's pair slots [S, E)
-    const uint32_t S = ws.bin_pstart[blockIdx.x];
-    const uint32_t E = S + ws.bin_ptot[blockIdx.x];
+    const uint32_t S = ws.bin_pstart[part];
+    const uint32_t E = S + ws.bin_ptot[part];
 
     for (int k = threadIdx.x; k < NW * kHash; k += NT) (&s_tab[0][0])[k] = 0ull;
-    const uint32_t *colp = ws.bin_cnt + (int64_t)blockIdx.x * ws.bin_tiles;
+    const uint32_t *colp = ws.bin_cnt + (int64_t)part * ws.bin_tiles;
     for (int t = threadIdx.x; t < b.tiles; t += NT)
         base[t] = ws.ranges[2 * ((int64_t)b.toff + t)] + colp[t];
 
@@ -490,10 +498,11 @@ hipError_t launch_bin_lists(const Ws &ws, const xg_camera *cams, const Params &p
     hipLaunchKernelGGL(k_bin_columns, dim3((unsigned)(ws.n_views * chunks)), dim3(kColThreads), 0, s, ws,
                        cams, p.tile, chunks);
     hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)ws.n_views), dim3(kStartThreads), 0, s, ws, cams, p.tile);
+    // kXcds extra workgroups write the blend launches' tile order
     if (ws.bin_tiles <= 1024)
-        hipLaunchKernelGGL((k_bin_scatter<1024, 16>), dim3(np), dim3(16 * kWave), 0, s, ws, cams, p.tile);
+        hipLaunchKernelGGL((k_bin_scatter<1024, 16>), dim3(np + kXcds), dim3(16 * kWave), 0, s, ws, cams, p.tile);
     else
-        hipLaunchKernelGGL((k_bin_scatter<4096, 8>), dim3(np), dim3(8 * kWave), 0, s, ws, cams, p.tile);
+        hipLaunchKernelGGL((k_bin_scatter<4096, 8>), dim3(np + kXcds), dim3(8 * kWave), 0, s, ws, cams, p.tile);
     return hipGetLastError();
 }
 

@@ -322,6 +322,38 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds, u
     return res;
 }
 
+// Work-order buckets of list lengths: eight per octave, longest first.
+constexpr int kOrderBuckets = 256;
+__device__ __forceinline__ int order_bucket(const Ws &ws, int64_t t) {
+    const uint32_t len = ws.ranges[2 * t + 1] - ws.ranges[2 * t];
+    const int l = (int)(8.0f * __log2f((float)len + 1.0f));
+    return kOrderBuckets - 1 - min(l, kOrderBuckets - 1);
+}
+
+// The blend launches' tile order, one XCD's part: the workgroup (at least
+// kOrderBuckets threads) orders the contiguous block of tiles that XCD x
+// renders (xcd_tile) by list length, longest first, and writes it over the
+// same block of xcd_order.  hist: kOrderBuckets words of LDS; scan_lds:
+// blockDim.x / 64 + 1 words.
+__device__ __forceinline__ void xcd_order_block(const Ws &ws, int x, uint32_t *hist, uint32_t *scan_lds) {
+    const int n = (int)ws.total_tiles;
+    const int q = n / kXcds, r = n % kXcds;
+    const int t0 = x * q + min(x, r), t1 = t0 + q + (x < r ? 1 : 0);
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) atomicAdd(&hist[order_bucket(ws, t)], 1u);
+    __syncthreads();
+    const uint32_t v = threadIdx.x < kOrderBuckets ? hist[threadIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, scan_lds, &tot);
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = ex;
+    __syncthreads();
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
+        const uint32_t pos = atomicAdd(&hist[order_bucket(ws, t)], 1u);
+        ws.xcd_order[t0 + (int)pos] = (int32_t)t;
+    }
+}
+
 // Resets the header words of a new frame other than the depth range.
 __device__ __forceinline__ void frame_header_reset(WsHeader *h) {
     h->status = XG_OK;

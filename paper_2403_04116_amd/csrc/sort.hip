@@ -548,7 +548,6 @@ __global__ __launch_bounds__(256) void k_ranges(Ws ws) {
 // the heaviest tiles start early and the tail of the launch stays short.
 // One workgroup; the order inside a bucket is arbitrary (it only affects
 // scheduling, not results).
-constexpr int kOrderBuckets = 256;
 
 __global__ __launch_bounds__(1024) void k_tile_order(Ws ws) {
     __shared__ uint32_t hist[kOrderBuckets];
@@ -556,11 +555,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(Ws ws) {
     const int64_t nt = ws.total_tiles;
     for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    auto key = [&](int64_t t) -> int {
-        const uint32_t len = ws.ranges[2 * t + 1] - ws.ranges[2 * t];
-        const int l = (int)(8.0f * __log2f((float)len + 1.0f));
-        return kOrderBuckets - 1 - min(l, kOrderBuckets - 1);
-    };
+    auto key = [&](int64_t t) -> int { return order_bucket(ws, t); };
     for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) atomicAdd(&hist[key(t)], 1u);
     __syncthreads();
     const uint32_t v = threadIdx.x < kOrderBuckets ? hist[threadIdx.x] : 0u;
@@ -574,34 +569,12 @@ __global__ __launch_bounds__(1024) void k_tile_order(Ws ws) {
     }
 }
 
-// The blend launches' tile order: workgroup x (one per XCD) orders the
-// contiguous block of tiles that XCD x renders (xcd_tile) by list length,
-// longest first, in the buckets of k_tile_order (eight per octave), and
-// writes it over the same block of xcd_order.
+// The blend launches' tile order as a launch of its own (one workgroup per
+// XCD), for the list paths whose last kernel does not write it.
 __global__ __launch_bounds__(1024) void k_xcd_order(Ws ws) {
     __shared__ uint32_t hist[kOrderBuckets];
     __shared__ uint32_t scan_lds[1024 / kWave + 1];
-    const int n = (int)ws.total_tiles;
-    const int x = blockIdx.x, q = n / kXcds, r = n % kXcds;
-    const int t0 = x * q + min(x, r), t1 = t0 + q + (x < r ? 1 : 0);
-    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
-    __syncthreads();
-    auto key = [&](int t) -> int {
-        const uint32_t len = ws.ranges[2 * (int64_t)t + 1] - ws.ranges[2 * (int64_t)t];
-        const int l = (int)(8.0f * __log2f((float)len + 1.0f));
-        return kOrderBuckets - 1 - min(l, kOrderBuckets - 1);
-    };
-    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) atomicAdd(&hist[key(t)], 1u);
-    __syncthreads();
-    const uint32_t v = threadIdx.x < kOrderBuckets ? hist[threadIdx.x] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(v, scan_lds, &tot);
-    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = ex;
-    __syncthreads();
-    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
-        const uint32_t pos = atomicAdd(&hist[key(t)], 1u);
-        ws.xcd_order[t0 + (int)pos] = (int32_t)t;
-    }
+    xcd_order_block(ws, blockIdx.x, hist, scan_lds);
 }
 
 // 64-bit sort keys of the sorted pairs, for inspection: keys[p] =
