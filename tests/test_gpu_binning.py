@@ -141,3 +141,28 @@ def test_radix_pair_sort_for_large_views():
     g = S.gaussians(8000, math.log(0.01), 0.3, 504)
     gpu, _ = _check(g, [0.4, 2.0], [(1100, 1100), (64, 64)], 8, "large view, radix path")
     assert int(gpu["frame"].total_tiles) == 138 * 138 + 64
+
+
+
+def test_tile_order_when_the_lists_are_empty():
+    """The blend launches read the tile order whatever the lists hold: after
+    a list build that exceeds the pair capacity (XG_ECAPACITY, every range
+    empty) and for a scene without Gaussians, each XCD block is still a
+    permutation of its tiles."""
+    import torch
+    import paper_2403_04116_amd as P
+    note("tile order with empty lists")
+    g = S.gaussians(3000, math.log(0.05), 0.3, 505)
+    sizes = [(200, 120), (64, 64), (37, 300)]
+    cams = P.cameras([0.2, 1.9, 3.3], sizes, S.L_SO, S.L_SD, S.DETECTOR_SIDE, S.DETECTOR_SIDE)
+    frame = P.Frame(3000, cams, P.settings(tile=8), pair_capacity=16, device="cuda")
+    gt = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda() for k in
+          ("means", "scales", "quats", "opacity", "intensity")}
+    frame.preprocess_sort(gt)
+    torch.cuda.synchronize()
+    assert frame.status() == P._lib.XG_ECAPACITY
+    _check_tile_order(frame, np.zeros((int(frame.total_tiles), 2), np.uint32))
+    g0 = {k: np.zeros((0,) + v.shape[1:], np.float32) for k, v in g.items()}
+    r = gpu_run(g0, [0.2, 1.9, 3.3], sizes, tile=8, backward=False)
+    assert r["status"] == 0 and r["keys"].size == 0
+    _check_tile_order(r["frame"], r["ranges"])
