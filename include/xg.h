@@ -71,7 +71,9 @@ typedef struct {
     float lowpass;         /* k of Sigma'' + k I (>= 0)                       */
     float alpha_min;       /* skip an evaluation with alpha < alpha_min      */
     float alpha_max;       /* clamp alpha to alpha_max (< 1)                  */
-    float t_min;           /* stop before transmittance drops below t_min    */
+    float t_min;           /* stop before transmittance drops below t_min
+                              (below the smallest normal float32, 2^-126,
+                              it acts as 2^-126)                              */
     float near_z;          /* cull Gaussians with camera depth <= near_z     */
     uint32_t flags;        /* XG_F_* bits                                     */
 } xg_settings;

@@ -34,6 +34,7 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math:
  * the key path needs IEEE binary32 round-to-nearest with no contraction).
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -395,6 +396,11 @@ static void blend_pixel(int32_t px, int32_t py, const int32_t *order, int64_t le
 {
     double T = 1.0, C = 0.0;
     double amin = st->alpha_min, amax = st->alpha_max, tmin = st->t_min;
+    /* t_min below the smallest normal float32 acts as that value (2^-126):
+     * the float32 transmittance of the GPU path stays normal, so that the
+     * recomputing backward can divide it back (the method's t_min, 1e-4,
+     * is far above) */
+    if (tmin < (double)FLT_MIN) tmin = (double)FLT_MIN;
     int32_t nflag = 0, flags = 0, evals = 0, nc = 0;
     res->last_pos = -1;
     res->last_idx = -1;

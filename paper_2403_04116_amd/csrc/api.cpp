@@ -9,6 +9,8 @@
 
 #include "common.h"
 
+#include <algorithm>
+#include <cfloat>
 #include <cmath>
 
 using namespace xg;
@@ -197,7 +199,10 @@ Params params_of(const xg_settings &s) {
     p.lowpass = s.lowpass;
     p.alpha_min = s.alpha_min;
     p.alpha_max = s.alpha_max;
-    p.t_min = s.t_min;
+    // a t_min below the smallest normal float32 acts as that value: the
+    // transmittance then stays a normal float, which the recomputing
+    // backward divides back contributor by contributor
+    p.t_min = std::max(s.t_min, FLT_MIN);
     p.near_z = s.near_z;
     // squared Mahalanobis radius beyond which o * exp(-m^2/2) < alpha_min
     // for any o <= 1; +inf when alpha_min == 0

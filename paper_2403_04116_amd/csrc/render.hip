@@ -573,9 +573,6 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
         last = n_contrib[o];
         if (g == 0.0f) last = 0;
     }
-    // recomputed variant: dL/dI times the transmittance, divided back one
-    // contributor at a time (T before a Gaussian = T after it / (1 - alpha))
-    float gTr = g * Tr;
     // stored variant: index of the next contributor (counting down) and its
     // stored transmittance, loaded one contributor ahead of its use;
     // contributors past the stored slots divide the transmittance back
@@ -666,10 +663,14 @@ __device__ __forceinline__ void bwd_tile(int tile, const Ws &ws, const xg_camera
                     Tr = Tj;
                     gT = g * Tj;
                 } else {
-                    // a lane that is not a contributor divides by 1 - 0 (the
-                    // reciprocal of 1 is exact) and keeps its value
-                    gT = gTr * __builtin_amdgcn_rcpf(1.0f - aact);
-                    gTr = gT;
+                    // T before this Gaussian = T after it / (1 - alpha); a
+                    // lane that is not a contributor divides by 1 - 0 (the
+                    // reciprocal of 1 is exact) and keeps its T.  T itself is
+                    // carried, not dL/dI x T: T stays a normal float down to
+                    // t_min, a product with a small dL/dI might not.
+                    const float Tj = Tr * __builtin_amdgcn_rcpf(1.0f - aact);
+                    Tr = Tj;
+                    gT = g * Tj;
                 }
                 const float it = sb.z;
                 float *v = acc[e];

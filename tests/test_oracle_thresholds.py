@@ -77,6 +77,21 @@ def test_termination_stack_hand_worked():
     assert r["flags"][0] == 0
 
 
+def test_zero_t_min_stops_at_the_smallest_normal_float():
+    """t_min = 0 acts as 2^-126 (the smallest normal float32): 130 Gaussians
+    with alpha = 1/2 give T = 2^-j after j contributors; the 127th would
+    take T to 2^-127 < 2^-126, so exactly 126 contribute, T = 2^-126 and
+    I = i (1 - 2^-126).  (The 126th lands on 2^-126 itself: not below, so it
+    is blended, and that decision is flagged as sitting on the threshold.)"""
+    st = O.Settings(alpha_min=1 / 255, t_min=0.0)
+    g = _stack(130, 0.5, 0.8)
+    r = O.render_brute(g, _cam(), st, _pix())
+    assert r["final_t"][0] == 2.0 ** -126
+    assert abs(r["image"][0] - 0.8 * (1 - 2.0 ** -126)) < 1e-12
+    assert r["last"][0] == 125
+    assert r["evals"][0] == 127
+
+
 def test_termination_ends_blending():
     """A Gaussian behind the stack that alone would not take T below t_min
     (alpha = 0.1: 2^-13 * 0.9 > 1e-4) must not change the pixel: blending
