@@ -116,7 +116,8 @@ __device__ __forceinline__ uint32_t subblock_mask(int xl, int xh, int yl, int yh
     return m;
 }
 
-// Smallest value over the box [X0, X1] x [Y0, Y1] of the exponent
+// Sub-block culling (in stage below): the smallest value over a box
+// [X0, X1] x [Y0, Y1] of the exponent
 // E(dx, dy) = (qa dx + qb dy)^2 + (qc dy)^2 (qa > 0, qb^2 + qc^2 > 0), whose
 // minimum 0 is at the origin.  For a box point p, the segment from p to the
 // origin leaves the box through an edge facing the origin, at a point q
@@ -201,17 +202,53 @@ __device__ __forceinline__ void stage(const Ws &ws, const uint32_t *vals, uint32
             const float oy = (float)(tg.y0 - tg.ry) + 0.5f - uy;
             const float rxl = ox + (float)xl, rxh = ox + (float)xh;
             const float ryl = oy + (float)yl, ryh = oy + (float)yh;
+            // A sub-block the rectangle touches has its edges on the right
+            // sides of the rectangle's: each clamp is a median of three (for
+            // the others the result is masked off).
+            if constexpr (SB > 2) {   // 32 x 32 tiles: one box at a time (registers)
+#pragma unroll
+                for (int sb = 0; sb < SB * SB; ++sb) {
+                    if (!((m >> sb) & 1u)) continue;
+                    const int bx = (sb % SB) * 8, by = (sb / SB) * 8;
+                    const float X0 = __builtin_amdgcn_fmed3f(rxl, ox + (float)bx, rxh);
+                    const float X1 = __builtin_amdgcn_fmed3f(rxl, ox + (float)(bx + 7), rxh);
+                    const float Y0 = __builtin_amdgcn_fmed3f(ryl, oy + (float)by, ryh);
+                    const float Y1 = __builtin_amdgcn_fmed3f(ryl, oy + (float)(by + 7), ryh);
+                    if (box_min_exponent(qa, qb, qc, rx, ry, X0, X1, Y0, Y1) > thr) mc &= ~(1u << sb);
+                }
+            } else {
+            // the same minimum with everything that depends on one coordinate
+            // only computed once per sub-block column (x) or row (y)
+            float X0[SB], X1[SB], xn[SB], ryxn[SB], qaxn[SB];
+            float Y0[SB], Y1[SB], yn[SB], rxyn[SB], qbyn[SB], e2s[SB];
+#pragma unroll
+            for (int c = 0; c < SB; ++c) {
+                X0[c] = __builtin_amdgcn_fmed3f(rxl, ox + (float)(8 * c), rxh);
+                X1[c] = __builtin_amdgcn_fmed3f(rxl, ox + (float)(8 * c + 7), rxh);
+                xn[c] = __builtin_amdgcn_fmed3f(0.0f, X0[c], X1[c]);
+                ryxn[c] = -ry * xn[c];
+                qaxn[c] = qa * xn[c];
+                Y0[c] = __builtin_amdgcn_fmed3f(ryl, oy + (float)(8 * c), ryh);
+                Y1[c] = __builtin_amdgcn_fmed3f(ryl, oy + (float)(8 * c + 7), ryh);
+                yn[c] = __builtin_amdgcn_fmed3f(0.0f, Y0[c], Y1[c]);
+                rxyn[c] = -rx * yn[c];
+                qbyn[c] = qb * yn[c];
+                const float e2 = qc * yn[c];
+                e2s[c] = e2 * e2;
+            }
 #pragma unroll
             for (int sb = 0; sb < SB * SB; ++sb) {
-                if (!((m >> sb) & 1u)) continue;
-                const int bx = (sb % SB) * 8, by = (sb / SB) * 8;
-                // the sub-block touches the rectangle, so its edges lie on the
-                // right sides of the rectangle's: each clamp is a median of three
-                const float X0 = __builtin_amdgcn_fmed3f(rxl, ox + (float)bx, rxh);
-                const float X1 = __builtin_amdgcn_fmed3f(rxl, ox + (float)(bx + 7), rxh);
-                const float Y0 = __builtin_amdgcn_fmed3f(ryl, oy + (float)by, ryh);
-                const float Y1 = __builtin_amdgcn_fmed3f(ryl, oy + (float)(by + 7), ryh);
-                if (box_min_exponent(qa, qb, qc, rx, ry, X0, X1, Y0, Y1) > thr) mc &= ~(1u << sb);
+                const int c = sb % SB, r = sb / SB;
+                // nearest point of the box to the centre along the edge x = x(y)
+                // facing it, and along y = y(x)
+                const float x = __builtin_amdgcn_fmed3f(rxyn[r], X0[c], X1[c]);
+                const float e1 = fmaf(qa, x, qbyn[r]);
+                const float E = fmaf(e1, e1, e2s[r]);
+                const float y = __builtin_amdgcn_fmed3f(ryxn[c], Y0[r], Y1[r]);
+                const float f1 = fmaf(qb, y, qaxn[c]), f2 = qc * y;
+                const float F = fmaf(f1, f1, f2 * f2);
+                if (fminf(E, F) > thr) mc &= ~(1u << sb);
+            }
             }
             if (CULL) m = mc;
             if (DUAL) s_cmask[k] = (uint16_t)mc;
