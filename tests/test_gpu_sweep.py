@@ -58,3 +58,43 @@ def test_random_scene(case):
     rg = O.backward(g, ref["cams"], ref["st"], upm, binned=(ref["pairs"]["values"], ref["pairs"]["ranges"]),
                     flip=m.flip)
     compare_grads(gpu["grads"], rg)
+
+
+def _cases_pst(k, seed):
+    rng = np.random.default_rng(seed)
+    for i in range(k):
+        n = int(rng.integers(50, 30000))
+        nv = int(rng.integers(1, 8))
+        sizes = [(int(rng.integers(8, 301)), int(rng.integers(8, 301))) for _ in range(nv)]
+        angles = rng.uniform(0, 2 * math.pi, nv).tolist()
+        tile = int(rng.choice([8, 16, 32]))
+        lds = int(rng.choice([64, 128, 256]))
+        lm = float(rng.uniform(math.log(0.01), math.log(0.1)))
+        ls = float(rng.uniform(0.2, 0.6))
+        mode = str(rng.choice(["persistent", "stored"]))
+        slots = int(rng.choice([1, 5, 40, 4096]))
+        s = int(rng.integers(0, 1 << 30))
+        yield i, n, sizes, angles, tile, lds, lm, ls, mode, slots, s
+
+
+@pytest.mark.parametrize("case", list(_cases_pst(12, 555)), ids=lambda c: f"case{c[0]}-{c[8]}")
+def test_random_scene_persistent_or_stored(case):
+    """The persistent tile queue (XG_F_PERSISTENT) and the stored-transmittance
+    variant (random slot counts, from 1 to more than any pixel needs) on
+    random scenes at the default thresholds."""
+    import test_gpu_store as TS
+    i, n, sizes, angles, tile, lds, lm, ls, mode, slots, seed = case
+    note(f"case {i}: {mode} slots={slots} n={n} views={sizes} tile={tile} lds={lds} seed={seed}")
+    g = S.gaussians(n, lm, ls, seed)
+    if mode == "stored":
+        TS._check(g, angles, sizes, slots, tile=tile, lds=lds, seed=seed)
+        return
+    ref = oracle_run(g, angles, sizes, tile=tile)
+    up = np.random.default_rng(seed + 1).normal(size=sum(w * h for w, h in sizes)).astype(np.float32)
+    upm = grad_upstream(up, ref)
+    gpu = gpu_run(g, angles, sizes, tile=tile, lds=lds, upstream=upm, persistent=True)
+    assert gpu["status"] == 0
+    m = compare_forward(gpu, ref, label=f"case {i} persistent")
+    rg = O.backward(g, ref["cams"], ref["st"], upm, binned=(ref["pairs"]["values"], ref["pairs"]["ranges"]),
+                    flip=m.flip)
+    compare_grads(gpu["grads"], rg)
